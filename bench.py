@@ -1,0 +1,193 @@
+"""Benchmark: contourlet forward + quantise + dequantise + inverse on 1080p frames.
+
+One step is the whole hot path on one batch: 16 synthetic 1920x1080 frames
+converted to YCoCg (48 float32 planes, padded to 1088 x 1920), LP 4 levels,
+DFB 32/16/8/8 directions, per-subband quantisation steps drawn per channel
+from 4..64. Inputs are resident in HBM before timing starts.
+
+Prints one JSON line. `value` is frames/s (real 1080p frames). The line also
+carries the effective HBM bandwidth of the step (algorithmic bytes / time),
+the roofline of the dominant kernel from live per-launch HIP events, and the
+FP64 oracle timed on the host cores on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "1080p frames/s for CT forward+inverse+quant; HBM GB/s as % of peak; batched vs plain"
+
+H, W, J, DIRS = 1080, 1920, 4, [32, 16, 8, 8]
+FRAMES = 16
+PLANES = 3 * FRAMES
+
+KERNEL_SOURCES = {
+    "lp_analysis": "ct_lp.hip", "lp_synthesis": "ct_lp.hip", "pad_fold": "ct_lp.hip",
+    "dfb12_analysis": "ct_dfb.hip", "dfb12_synthesis": "ct_dfb.hip",
+    "dfb_split_analysis": "ct_dfb.hip", "dfb_split_synthesis": "ct_dfb.hip",
+    "lowpass_partial": "ct_quant.hip", "quantize": "ct_quant.hip", "dequantize": "ct_quant.hip",
+}
+
+
+def algorithmic_bytes_per_plane(ncoef):
+    """Forward 4HW + 4n, quantise 4n + 2n, dequantise 2n + 4n, inverse 4n + 4HW."""
+    return 8 * H * W + 20 * ncoef
+
+
+def source_digest(name):
+    path = os.path.join(ROOT, "paper_1510_00561_amd", "csrc", KERNEL_SOURCES[name])
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(name, bytes_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if current."""
+    path = os.path.join(ROOT, "profiles", "traffic_1080p.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    ent = data.get("kernels", {}).get(name)
+    if not ent or ent.get("source_sha256_16") != source_digest(name):
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(planes_np, steps_np, seconds_budget=30.0):
+    """The FP64 oracle on one 1080p YCoCg frame (3 planes), single process."""
+    import numpy as np
+    from oracle import ct as oct
+    from oracle import geometry as geo
+    from oracle import quant as oq
+    table = geo.subband_table(H, W, J, DIRS)
+    t0 = time.perf_counter()
+    n = 0
+    for b in range(3):
+        x = planes_np[b].astype(np.float64)
+        c = oct.forward(x, J, DIRS)
+        q, side = oq.quantize64(c, steps_np[b % 3].astype(np.float64), table)
+        d = oq.dequantize64(q, steps_np[b % 3].astype(np.float64), side, table)
+        oct.inverse(d, H, W, J, DIRS)
+        n += 1
+        if time.perf_counter() - t0 > seconds_budget:
+            break
+    dt = time.perf_counter() - t0
+    frames = n / 3.0
+    return {"value": frames / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} of the 3 planes of one 1080p YCoCg frame, forward+quantise+dequantise+inverse "
+                      f"in FP64 NumPy, one process ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1510_00561_amd import ct, synth
+
+    print(f"[bench] generating {FRAMES} frames of {W}x{H}", file=sys.stderr, flush=True)
+    planes_np = synth.clip_planes(FRAMES, H, W, 3)
+    plan = ct.Plan(H, W, J, DIRS, PLANES, "cuda:0")
+    steps_tab = synth.subband_steps(plan.nsub, 3, 3)            # [3][nsub]
+    steps_np = np.stack([steps_tab[b % 3] for b in range(PLANES)]).astype(np.float32)
+
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(planes_np).to(dev)
+    steps = torch.from_numpy(steps_np).to(dev)
+    coef = torch.empty((PLANES, plan.ncoef), dtype=torch.float32, device=dev)
+    coef2 = torch.empty_like(coef)
+    idx = torch.empty((PLANES, plan.ncoef), dtype=torch.int16, device=dev)
+    side = torch.empty((PLANES, 2), dtype=torch.float32, device=dev)
+    rec = torch.empty_like(x)
+
+    def step():
+        plan.forward(x, out=coef)
+        plan.quantize(coef, steps, idx, side)
+        plan.dequantize(idx, steps, side, out=coef2)
+        plan.inverse(coef2, out=rec)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    err = float((rec - x).abs().max())
+
+    alg = algorithmic_bytes_per_plane(plan.ncoef) * PLANES
+    fps = FRAMES / (ms / 1e3)
+    eff_gbps = alg / (ms / 1e3) / 1e9
+
+    roofline = None
+    kernels = {}
+    if not args.no_profile:
+        ct.profile_enable(True, 8192)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        stats = ct.profile_collect()
+        ct.profile_enable(False)
+        total = sum(v[1] for v in stats.values())
+        for name, (n, tms, by) in stats.items():
+            kernels[name] = {"launches_per_step": n / args.steps, "ms_per_step": tms / args.steps,
+                             "share": tms / total if total else 0.0,
+                             "gbps": by / (tms / 1e3) / 1e9 if tms else 0.0}
+        dom = max(stats.items(), key=lambda kv: kv[1][1])
+        name, (n, tms, by) = dom
+        achieved = by / (tms / 1e3) / 1e9
+        traffic = measured_traffic(name, by / n)
+        roofline = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                    "traffic": traffic, "avg_launch_us": round(tms / n * 1e3, 2),
+                    "bytes_per_launch": by / n}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(planes_np, steps_tab)
+
+    out = {
+        "metric": METRIC, "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "16 x 1920x1080 YCoCg frames (48 planes, padded 1088x1920), "
+                               "CT J=4 dirs 32/16/8/8, forward+quantise+dequantise+inverse, "
+                               "per-subband steps 4..64",
+                   "frames": FRAMES, "planes": PLANES, "levels": J, "dirs": DIRS},
+        "hbm_effective_gbps": round(eff_gbps, 1),
+        "hbm_effective_frac": round(eff_gbps / HBM_PEAK_GBPS, 4),
+        "algorithmic_bytes_per_step": alg,
+        "roundtrip_max_abs_err": err,
+        "wall_s": round(wall, 3),
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * ct.h - C ABI of the MI355X contourlet transform library (libct.so).
+ *
+ * The contourlet transform (CT) of CVC: a Laplacian pyramid (LP) whose
+ * bandpass image at every level is split by a directional filter bank (DFB)
+ * into 2^l wedge-shaped subbands, iterated on the lowpass (paper section 2.1,
+ * Fig. 1), with the 9-7 biorthogonal filters for both (section 2.1). The
+ * output of a plane is the coarsest lowpass plus the directional subbands of
+ * every scale (section 3.3). The lowpass is then normalised to [0, 255]
+ * (section 3.4) and every coefficient is divided by a quantisation step and
+ * rounded to the nearest integer (sections 3.5, 3.6).
+ *
+ * Conventions shared by every call
+ *   - A "plane" is one H x W float32 image, row major. A batch is B planes
+ *     stored back to back ([B][H][W]).
+ *   - Coefficients of one plane form a packed float32 vector of `ncoef`
+ *     entries ([B][ncoef] for a batch), laid out as described by
+ *     ct_layout_query: the lowpass, then levels from coarse to fine, each
+ *     level's subbands in direction order.
+ *   - Data pointers are DEVICE pointers owned by the caller. The library never
+ *     frees or retains them. It allocates no device memory in these calls:
+ *     scratch space comes from the caller's workspace `ws` of `ws_bytes`
+ *     bytes (at least ct_workspace_bytes()).
+ *   - Every compute call only enqueues work on `stream` and returns without
+ *     synchronising. Faults inside kernels surface at the caller's next
+ *     synchronisation on that stream.
+ *   - All argument and geometry validation happens on the host before any
+ *     launch, so an error return means nothing was enqueued.
+ *   - Return value: CT_OK (0) on success, a negative CT_ERR_* code otherwise.
+ *     No call aborts, exits or throws across this boundary.
+ *   - Calls are reentrant. Two calls that share output or workspace buffers
+ *     must be ordered by the caller (same stream, or events).
+ */
+#ifndef CT_H_
+#define CT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CT_MAX_LEVELS 6
+
+enum {
+    CT_OK = 0,
+    CT_ERR_ARG = -1,          /* null pointer, batch < 0, bad sizes          */
+    CT_ERR_GEOM = -2,         /* geometry outside the supported range        */
+    CT_ERR_WORKSPACE = -3,    /* workspace smaller than ct_workspace_bytes() */
+    CT_ERR_HIP = -4,          /* a HIP runtime call failed                   */
+    CT_ERR_UNSUPPORTED = -5   /* valid request this build does not serve     */
+};
+
+/*
+ * Geometry of one plane.
+ *   height, width  unpadded plane size (each >= 2^e, see ct_layout).
+ *   levels         J, number of LP levels, 1..6 (section 3.3).
+ *   dirs[j]        directional subbands at LP level j+1; dirs[0] is the
+ *                  finest level. Each a power of two in [4, 64] (2^l wedges
+ *                  at DFB level l, section 2.1). Entries at j >= levels are
+ *                  ignored.
+ */
+typedef struct ct_geom {
+    int32_t height, width;
+    int32_t levels;
+    int32_t dirs[CT_MAX_LEVELS];
+} ct_geom;
+
+/*
+ * Derived layout of one plane.
+ *   pad_h, pad_w   R, C: the periodic working size. Each side is rounded up
+ *                  to a multiple of 2^e, e = max(J, max_j (j + log2 dirs_j - 2)).
+ *                  The extra rows/columns mirror the plane about its last
+ *                  sample (x[H+i] = x[H-1-i]); the inverse crops them off.
+ *   exp2           e.
+ *   ncoef          coefficients per plane = sum of all subband sizes.
+ *   nsub           1 + sum_j dirs[j] (entry 0 is the lowpass).
+ */
+typedef struct ct_layout {
+    int32_t pad_h, pad_w;
+    int32_t exp2;
+    int32_t nsub;
+    int64_t ncoef;
+} ct_layout;
+
+/*
+ * One subband of the packed layout.
+ *   level      LP level j (1 = finest); the lowpass has level = J + 1.
+ *   k          direction index within the level (-1 for the lowpass). Order:
+ *              by wedge angle atan2(w1, w2) over (-45, 135) degrees:
+ *              horizontal cone (|w2| > |w1|) first, then vertical cone.
+ *   rows, cols natural size of the subband array.
+ *   offset     first element within the plane's packed vector.
+ *   o1, o2     lattice offset of sample (0, 0) in level-j image coordinates.
+ *   s1, s2     lattice steps: sample (i, k) is level pixel (o1 + s1 i, o2 + s2 k).
+ *   transposed 1 if stored as the transpose of the natural array (row major
+ *              cols x rows): the vertical-cone subbands.
+ */
+typedef struct ct_subband {
+    int32_t level, k;
+    int32_t rows, cols;
+    int64_t offset;
+    int32_t o1, o2;
+    int32_t s1, s2;
+    int32_t transposed;
+    int32_t reserved;
+} ct_subband;
+
+/*
+ * Host-only query of the layout (no GPU needed).
+ * Fills *out, and the first min(cap, nsub) entries of `table` (table may be
+ * NULL when cap is 0). Returns CT_ERR_ARG for null geom/out, CT_ERR_GEOM for
+ * an unsupported geometry.
+ */
+int ct_layout_query(const ct_geom* geom, ct_layout* out, ct_subband* table, int32_t cap);
+
+/*
+ * Workspace needed by ct_forward/ct_inverse/ct_quantize and the adjoints for
+ * `batch` planes, in bytes (host only). Writes 0 and returns an error code
+ * on bad input.
+ */
+int ct_workspace_bytes(const ct_geom* geom, int32_t batch, size_t* bytes);
+
+/*
+ * Forward CT (encoder, sections 2.1 and 3.3).
+ *   planes  [batch][H][W] float32 input.
+ *   coeffs  [batch][ncoef] float32 output, packed layout.
+ */
+int ct_forward(const ct_geom* geom, int32_t batch, const float* planes, float* coeffs,
+               void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Inverse CT (decoder): exact inverse of ct_forward on unquantised
+ * coefficients; LP reconstruction uses the dual frame (c' = c - H d,
+ * x = d + G up(c')).
+ *   coeffs  [batch][ncoef] float32 input.
+ *   planes  [batch][H][W] float32 output (padding cropped).
+ */
+int ct_inverse(const ct_geom* geom, int32_t batch, const float* coeffs, float* planes,
+               void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Quantise (sections 3.4-3.6). Per plane b:
+ *   lowpass (subband 0): mn = min, mx = max over the plane's lowpass;
+ *     s = 255/(mx - mn) (s = 0 when mx == mn); q = round(((c - mn) * s) / step[0])
+ *   directional subband i >= 1: q = round(c / step[i])
+ *   round = nearest, halves away from zero; saturated to int16; NaN -> 0.
+ * All arithmetic in IEEE float32, in exactly this order, correctly rounded.
+ *   steps       device float32 [batch][steps_stride] step table per plane; entry
+ *               i of a row is the step of subband i (ct_subband order). Use
+ *               steps_stride = 0 to share one row of nsub steps by all planes.
+ *               Steps must be finite and > 0.
+ *   idx         [batch][ncoef] int16 output.
+ *   side        [batch][2] float32 output: (mn, mx) of each plane's lowpass.
+ */
+int ct_quantize(const ct_geom* geom, int32_t batch, const float* coeffs, const float* steps,
+                int32_t steps_stride, int16_t* idx, float* side,
+                void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Dequantise (the decoder side of sections 3.4-3.5):
+ *   directional  c = q * step[i]
+ *   lowpass      c = mn + (q * step[0]) * ((mx - mn) / 255)
+ * float32, in this order.
+ */
+int ct_dequantize(const ct_geom* geom, int32_t batch, const int16_t* idx, const float* steps,
+                  int32_t steps_stride, const float* side, float* coeffs, hipStream_t stream);
+
+/*
+ * Transposes for the differentiable form (gradients through the CT).
+ * ct_forward_adjoint computes F^T g: gcoeffs [batch][ncoef] -> gplanes [batch][H][W].
+ * ct_inverse_adjoint computes S^T g: gplanes [batch][H][W] -> gcoeffs [batch][ncoef].
+ * The frame is not tight, so F^T differs from the inverse S.
+ */
+int ct_forward_adjoint(const ct_geom* geom, int32_t batch, const float* gcoeffs, float* gplanes,
+                       void* ws, size_t ws_bytes, hipStream_t stream);
+int ct_inverse_adjoint(const ct_geom* geom, int32_t batch, const float* gplanes, float* gcoeffs,
+                       void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Per-kernel timing (HIP events), for benchmarks and tracing.
+ * ct_profile_enable(1) creates a pool of `max_launches` event pairs (0 picks
+ * 16384) and makes every later launch record one event before and one after
+ * itself on its stream; ct_profile_enable(0) stops recording and releases
+ * the pool. Recording adds two event packets per launch and allocates
+ * nothing on the device.
+ * ct_profile_collect waits for the recorded events, aggregates them by
+ * kernel (name, launches, total milliseconds, compulsory bytes = inputs read
+ * once + outputs written once), writes up to `cap` entries, sets *n to the
+ * number of kernels seen, and clears the record. Returns CT_ERR_HIP if an
+ * event query fails, CT_ERR_UNSUPPORTED if launches were dropped because
+ * the pool ran out.
+ */
+typedef struct ct_kernel_stat {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+    double bytes;
+} ct_kernel_stat;
+int ct_profile_enable(int32_t on, int32_t max_launches);
+int ct_profile_collect(ct_kernel_stat* out, int32_t cap, int32_t* n);
+
+/* Human-readable text for a CT_ERR_* code (static storage). */
+const char* ct_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CT_H_ */

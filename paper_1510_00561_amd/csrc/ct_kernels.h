@@ -1,0 +1,110 @@
+// Kernel parameter blocks and launch wrappers (device side of libct).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ct {
+
+// One-sided taps of a symmetric filter: t[0] centre, t[k] = tap at +-k.
+struct Taps5 {
+    float t[5];
+};
+
+// Four lifting constants; step s updates the sub-coset of parity
+// (first_odd + s) & 1 from the other one.
+struct Lift {
+    float c[4];
+    int first_odd;
+};
+
+// A 2-D strided array of planes.
+struct View {
+    float* p;
+    int64_t plane;   // elements between planes
+    int ld;          // elements between rows
+};
+
+struct CView {
+    const float* p;
+    int64_t plane;
+    int ld;
+};
+
+// How the level-1 analysis reads beyond the real frame.
+enum PadMode { kPadNone = 0, kPadReflect = 1, kPadZero = 2 };
+
+// LP analysis level: c = down2(lo * x), d = x - up * up2(c). `lo_r`
+// selects the reach of lo (4 for hbar, 3 for gbar); `up_r` that of up.
+hipError_t launch_lp_analysis(CView src, int src_h, int src_w, int pad_mode, int R, int C,
+                              View c_out, View d_out, Taps5 lo, int lo_r, Taps5 up, int up_r,
+                              int batch, hipStream_t s);
+
+// LP dual synthesis level: c' = c - down2(lo * d), x = d + up * up2(c').
+// Writes rows < out_h and cols < out_w of the R x C result.
+hipError_t launch_lp_synthesis(CView c_in, CView d_in, int R, int C, View x_out, int out_h,
+                               int out_w, Taps5 lo, int lo_r, Taps5 up, int up_r, int batch,
+                               hipStream_t s);
+
+// Output/input description of the four tree-level-2 channels, in subband
+// order: [H a=-1 (coset (0,1)), H a=0 (1,0), V a=0 (0,0), V a=-1 (1,1)].
+// Horizontal channels are (R/2) x (C/2) row major; vertical channels are
+// stored transposed, (C/2) x (R/2).
+struct Quad {
+    float* p[4];
+    int64_t plane;
+    float scale[4];
+};
+
+// DFB tree levels 1 and 2 on a level image: analysis (d -> 4 channels) and
+// synthesis (4 channels -> d).
+hipError_t launch_dfb12_analysis(CView d, int R, int C, Quad out, Lift lift, int batch,
+                                 hipStream_t s);
+hipError_t launch_dfb12_synthesis(Quad in, int R, int C, View d, Lift lift, int batch,
+                                  hipStream_t s);
+
+// One DFB tree level t >= 3 for all channels of an LP level whose image is
+// R_j x C_j. Channels of a tree level are stored back to back in subband
+// order; horizontal channels as (R_j / 2^(t-1)) x (C_j / 2), vertical ones
+// transposed as (C_j / 2^(t-1)) x (R_j / 2).
+struct SplitArgs {
+    int t;              // tree level of the split (children level)
+    int Rj, Cj;         // level image size
+    const float* parent;
+    float* child;
+    int64_t plane_elems; // elements per plane in both buffers (Rj * Cj)
+    int64_t parent_plane, child_plane;  // plane strides of the two buffers
+    float scale[64];    // per child channel (applied on store / load)
+    int use_scale;
+};
+hipError_t launch_dfb_split_analysis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
+hipError_t launch_dfb_split_synthesis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
+
+// Folds the mirrored padding back onto its sources (transpose of padding):
+// out[r][c] = sum of in[r'][c'] over r' in {r, 2H-1-r}, c' in {c, 2W-1-c}
+// restricted to [0, R) x [0, C).
+hipError_t launch_pad_fold(CView in, int R, int C, View out, int H, int W, int batch,
+                           hipStream_t s);
+
+// Quantiser.
+struct QuantArgs {
+    const float* coeffs;
+    const int16_t* idx_in;
+    float* coeffs_out;
+    int16_t* idx;
+    float* side;
+    const float* steps;
+    int steps_stride;
+    float* partials;         // [batch][kMaxPart][2]
+    int64_t ncoef;
+    int64_t low_n;
+    int nsub;
+    int nparts;              // partial blocks per plane for the lowpass
+    int sub_off[386];        // subband start offsets + end sentinel
+};
+// Pass 1 (per-block lowpass min/max partials) and pass 2 (indices).
+hipError_t launch_lowpass_partial(const QuantArgs& a, int batch, hipStream_t s);
+hipError_t launch_quantize(const QuantArgs& a, int batch, hipStream_t s);
+hipError_t launch_dequantize(const QuantArgs& a, int batch, hipStream_t s);
+
+}  // namespace ct

@@ -1,0 +1,116 @@
+"""Host-side tests of the C ABI (no kernel launches): exports, layout, validation."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import geometry as geo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ct.h")
+
+
+@pytest.fixture(scope="module")
+def ct():
+    from paper_1510_00561_amd import ct as ctmod
+    if not os.path.exists(ctmod.LIB_PATH):
+        from paper_1510_00561_amd import build
+        build.build()
+    return ctmod
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ct_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(ct):
+    lib = ct._lib()
+    names = declared_functions()
+    assert "ct_forward" in names and "ct_quantize" in names
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in ct.h but not exported"
+
+
+GEOMS = [
+    (256, 256, 2, [8, 4]),
+    (480, 640, 3, [16, 8, 4]),
+    (1080, 1920, 4, [32, 16, 8, 8]),
+    (720, 1280, 3, [16, 8, 4]),
+    (240, 320, 4, [16, 8, 8, 8]),
+    (70, 90, 3, [16, 8, 4]),
+    (128, 128, 1, [64]),
+    (64, 96, 2, [4, 32]),
+]
+
+
+@pytest.mark.parametrize("H,W,J,dirs", GEOMS)
+def test_layout_matches_oracle(ct, H, W, J, dirs):
+    lay, table = ct.layout(H, W, J, dirs)
+    ref = geo.subband_table(H, W, J, dirs)
+    R, C = geo.padded_size(H, W, J, dirs)
+    assert (lay.pad_h, lay.pad_w) == (R, C)
+    assert lay.exp2 == geo.pad_exponent(J, dirs)
+    assert lay.ncoef == geo.ncoef(H, W, J, dirs)
+    assert lay.nsub == len(ref)
+    for got, want in zip(table, ref):
+        assert (got.level, got.k, got.rows, got.cols, got.offset) == \
+               (want.level, want.k, want.rows, want.cols, want.offset)
+        assert (got.o1, got.o2, got.s1, got.s2, bool(got.transposed)) == \
+               (want.o1, want.o2, want.s1, want.s2, want.transposed)
+
+
+@pytest.mark.parametrize("H,W,J,dirs", [
+    (256, 256, 0, []),
+    (256, 256, 7, [4] * 6),
+    (256, 256, 2, [8, 6]),
+    (256, 256, 2, [128, 4]),
+    (256, 256, 2, [2, 4]),
+    (8, 256, 2, [32, 4]),
+    (0, 256, 1, [4]),
+])
+def test_layout_rejects_bad_geometry(ct, H, W, J, dirs):
+    g = ct.geom(H, W, J, dirs[:6])
+    lay = ct.Layout()
+    assert ct._lib().ct_layout_query(ctypes.byref(g), ctypes.byref(lay), None, 0) == -2
+
+
+def test_null_arguments(ct):
+    lib = ct._lib()
+    g = ct.geom(256, 256, 2, [8, 4])
+    assert lib.ct_layout_query(None, None, None, 0) == -1
+    assert lib.ct_layout_query(ctypes.byref(g), None, None, 0) == -1
+    n = ctypes.c_size_t(7)
+    assert lib.ct_workspace_bytes(ctypes.byref(g), -1, ctypes.byref(n)) == -1 and n.value == 0
+    dummy = ctypes.c_void_p(0x1000)
+    # validation fails before any launch
+    assert lib.ct_forward(ctypes.byref(g), 1, None, dummy, dummy, 1 << 40, None) == -1
+    assert lib.ct_inverse(ctypes.byref(g), 1, dummy, None, dummy, 1 << 40, None) == -1
+    assert lib.ct_forward(ctypes.byref(g), -3, dummy, dummy, dummy, 1 << 40, None) == -1
+    assert lib.ct_quantize(ctypes.byref(g), 1, dummy, None, 0, dummy, dummy, dummy, 1 << 40, None) == -1
+    assert lib.ct_dequantize(ctypes.byref(g), 1, dummy, dummy, 3, dummy, dummy, None) == -1  # stride < nsub
+    assert lib.ct_forward(ctypes.byref(g), 0, None, None, None, 0, None) == 0   # empty batch
+
+
+def test_workspace_too_small(ct):
+    lib = ct._lib()
+    g = ct.geom(256, 256, 2, [8, 4])
+    need = ct.workspace_bytes(256, 256, 2, [8, 4], 3)
+    assert need >= 3 * 256 * 256 * 4 * 3
+    dummy = ctypes.c_void_p(0x1000)
+    for fn in ("ct_forward", "ct_inverse", "ct_forward_adjoint", "ct_inverse_adjoint"):
+        assert getattr(lib, fn)(ctypes.byref(g), 3, dummy, dummy, dummy, need - 1, None) == -3
+    assert lib.ct_quantize(ctypes.byref(g), 3, dummy, dummy, 0, dummy, dummy, dummy, need - 1, None) == -3
+
+
+def test_fault_injection_hook(ct, monkeypatch):
+    lib = ct._lib()
+    g = ct.geom(256, 256, 2, [8, 4])
+    need = ct.workspace_bytes(256, 256, 2, [8, 4], 1)
+    dummy = ctypes.c_void_p(0x1000)
+    monkeypatch.setenv("CT_FAULT_INJECT", "launch")
+    assert lib.ct_forward(ctypes.byref(g), 1, dummy, dummy, dummy, need, None) == -4
+    assert lib.ct_quantize(ctypes.byref(g), 1, dummy, dummy, 0, dummy, dummy, dummy, need, None) == -4
+    assert lib.ct_strerror(-4) == b"HIP runtime error"
