@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
+                    help="copy: stream 1 GiB through a plain elementwise kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -99,6 +101,17 @@ def main():
     import numpy as np
     import torch
     from paper_1510_00561_amd import ct, synth
+
+    if args.mode == "copy":
+        n = 1 << 28                                   # 2^28 floats = 1 GiB each way
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                          "launches": args.steps}))
+        return
 
     print(f"[bench] generating {FRAMES} frames of {W}x{H}", file=sys.stderr, flush=True)
     planes_np = synth.clip_planes(FRAMES, H, W, 3)
