@@ -32,6 +32,8 @@ KERNEL_SOURCES = {
     "dfb12_analysis": "ct_dfb.hip", "dfb12_synthesis": "ct_dfb.hip",
     "dfb_split_analysis": "ct_dfb.hip", "dfb_split_synthesis": "ct_dfb.hip",
     "lowpass_partial": "ct_quant.hip", "quantize": "ct_quant.hip", "dequantize": "ct_quant.hip",
+    "lp_dfb12_analysis": "ct_level.hip", "dfb12_lp_synthesis": "ct_level.hip",
+    "dfb_split2_analysis": "ct_dfb.hip", "dfb_split2_synthesis": "ct_dfb.hip",
 }
 
 

@@ -22,6 +22,7 @@ SOURCES = [
     ("ct_api.cpp", []),
     ("ct_lp.hip", []),
     ("ct_dfb.hip", []),
+    ("ct_level.hip", []),
     ("ct_quant.hip", ["-ffp-contract=off"]),
 ]
 

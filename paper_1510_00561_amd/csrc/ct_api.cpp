@@ -138,6 +138,18 @@ int check_common(const ct_geom* geom, int32_t batch, Geometry* g) {
     return resolve(geom, g);
 }
 
+// Groups of DFB tree levels >= 3 run per pass: pairs from the top, then a
+// single trailing level when their count is odd.
+int split_groups(int l, int* first, int* count) {
+    int n = 0;
+    for (int t = 3; t <= l; t += 2) {
+        first[n] = t;
+        count[n] = (t + 1 <= l) ? 2 : 1;
+        ++n;
+    }
+    return n;
+}
+
 // Analysis direction: image -> coefficients (forward, inverse adjoint).
 int run_analysis(const Geometry& g, int batch, const float* planes, float* coeffs, char* ws,
                  const Workspace& w, Mode mode, hipStream_t st) {
@@ -147,7 +159,6 @@ int run_analysis(const Geometry& g, int batch, const float* planes, float* coeff
     const int lo_r = fwd ? 4 : 3, up_r = fwd ? 3 : 4;
     const Lift L = lift_for(mode);
     const int64_t RC = int64_t(g.R) * g.C;
-    float* D = reinterpret_cast<float*>(ws + w.d_off);
     float* A = reinterpret_cast<float*>(ws + w.a_off);
     float* Bf = reinterpret_cast<float*>(ws + w.b_off);
     for (int j = 1; j <= g.J; ++j) {
@@ -165,12 +176,6 @@ int run_analysis(const Geometry& g, int batch, const float* planes, float* coeff
         View c_out = (j == g.J)
                          ? View{coeffs, g.ncoef, Cj / 2}
                          : View{reinterpret_cast<float*>(ws + w.c_off[j]), int64_t(Rj / 2) * (Cj / 2), Cj / 2};
-        View d_out{D, RC, Cj};
-        const double lp_bytes = 4.0 * batch *
-            (double(src_h) * src_w + double(Rj / 2) * (Cj / 2) + double(Rj) * Cj);
-        CT_LAUNCH("lp_analysis", lp_bytes,
-                  launch_lp_analysis(src, src_h, src_w, pad, Rj, Cj, c_out, d_out, lo, lo_r, up,
-                                     up_r, batch, st));
         const int l = g.l[j - 1];
         float* level = coeffs + g.level_off[j];
         const int64_t q4 = int64_t(Rj) * Cj / 4;
@@ -191,20 +196,26 @@ int run_analysis(const Geometry& g, int batch, const float* planes, float* coeff
             quad.plane = RC;
         }
         const double lvl_bytes = 8.0 * batch * double(Rj) * Cj;
-        CT_LAUNCH("dfb12_analysis", lvl_bytes,
-                  launch_dfb12_analysis(CView{D, RC, Cj}, Rj, Cj, quad, L, batch, st));
+        const double lp_bytes = 4.0 * batch *
+            (double(src_h) * src_w + double(Rj / 2) * (Cj / 2) + double(Rj) * Cj);
+        CT_LAUNCH("lp_dfb12_analysis", lp_bytes,
+                  launch_lp_dfb12_analysis(src, src_h, src_w, pad, Rj, Cj, c_out, quad, lo, lo_r,
+                                           up, up_r, L, batch, st));
+        int first[4], count[4];
+        const int ng = split_groups(l, first, count);
         float* cur = A;
         float* other = Bf;
-        for (int t = 3; t <= l; ++t) {
+        for (int gi = 0; gi < ng; ++gi) {
+            const bool last = gi == ng - 1;
             SplitArgs a;
             memset(&a, 0, sizeof(a));
-            a.t = t;
+            a.t = first[gi];
             a.Rj = Rj;
             a.Cj = Cj;
             a.parent = cur;
             a.parent_plane = RC;
             a.plane_elems = int64_t(Rj) * Cj;
-            if (t == l) {
+            if (last) {
                 a.child = level;
                 a.child_plane = g.ncoef;
                 a.use_scale = 1;
@@ -213,7 +224,10 @@ int run_analysis(const Geometry& g, int batch, const float* planes, float* coeff
                 a.child = other;
                 a.child_plane = RC;
             }
-            CT_LAUNCH("dfb_split_analysis", lvl_bytes, launch_dfb_split_analysis(a, L, batch, st));
+            if (count[gi] == 2)
+                CT_LAUNCH("dfb_split2_analysis", lvl_bytes, launch_dfb_split2_analysis(a, L, batch, st));
+            else
+                CT_LAUNCH("dfb_split_analysis", lvl_bytes, launch_dfb_split_analysis(a, L, batch, st));
             float* tmp = cur;
             cur = other;
             other = tmp;
@@ -250,18 +264,20 @@ int run_synthesis(const Geometry& g, int batch, const float* coeffs, float* plan
             }
             quad.plane = g.ncoef;
         } else {
+            int first[4], count[4];
+            const int ng = split_groups(l, first, count);
             float* cur = A;
             float* other = Bf;
-            for (int t = l; t >= 3; --t) {
+            for (int gi = ng - 1; gi >= 0; --gi) {
                 SplitArgs a;
                 memset(&a, 0, sizeof(a));
-                a.t = t;
+                a.t = first[gi];
                 a.Rj = Rj;
                 a.Cj = Cj;
                 a.plane_elems = int64_t(Rj) * Cj;
                 a.child = cur;            // output: the parents
                 a.child_plane = RC;
-                if (t == l) {
+                if (gi == ng - 1) {
                     a.parent = level;     // input: the final subbands
                     a.parent_plane = g.ncoef;
                     a.use_scale = 1;
@@ -270,21 +286,23 @@ int run_synthesis(const Geometry& g, int batch, const float* coeffs, float* plan
                     a.parent = other;
                     a.parent_plane = RC;
                 }
-                CT_LAUNCH("dfb_split_synthesis", lvl_bytes,
-                          launch_dfb_split_synthesis(a, L, batch, st));
+                if (count[gi] == 2)
+                    CT_LAUNCH("dfb_split2_synthesis", lvl_bytes,
+                              launch_dfb_split2_synthesis(a, L, batch, st));
+                else
+                    CT_LAUNCH("dfb_split_synthesis", lvl_bytes,
+                              launch_dfb_split_synthesis(a, L, batch, st));
                 float* tmp = cur;
                 cur = other;
                 other = tmp;
             }
-            // the last split wrote into `other` (after the swap)
+            // the last pass wrote into `other` (after the swap)
             for (int k = 0; k < 4; ++k) {
                 quad.p[k] = other + k * q4;
                 quad.scale[k] = 1.f;
             }
             quad.plane = RC;
         }
-        CT_LAUNCH("dfb12_synthesis", lvl_bytes,
-                  launch_dfb12_synthesis(quad, Rj, Cj, View{D, RC, Cj}, L, batch, st));
         CView c_in = (j == g.J)
                          ? CView{coeffs, g.ncoef, Cj / 2}
                          : CView{reinterpret_cast<const float*>(ws + w.c_off[j]), int64_t(Rj / 2) * (Cj / 2), Cj / 2};
@@ -295,19 +313,19 @@ int run_synthesis(const Geometry& g, int batch, const float* coeffs, float* plan
             out_h = g.H;
             out_w = g.W;
         } else if (j == 1) {
-            x_out = View{A, RC, g.C};
+            x_out = View{D, RC, g.C};
         } else {
             x_out = View{reinterpret_cast<float*>(ws + w.c_off[j - 1]), int64_t(Rj) * Cj, Cj};
         }
         const double lps_bytes = 4.0 * batch *
             (double(Rj / 2) * (Cj / 2) + double(Rj) * Cj + double(out_h) * out_w);
-        CT_LAUNCH("lp_synthesis", lps_bytes,
-                  launch_lp_synthesis(c_in, CView{D, RC, Cj}, Rj, Cj, x_out, out_h, out_w, lo,
-                                      lo_r, up, up_r, batch, st));
+        CT_LAUNCH("dfb12_lp_synthesis", lps_bytes,
+                  launch_dfb12_lp_synthesis(quad, c_in, Rj, Cj, x_out, out_h, out_w, lo, lo_r, up,
+                                            up_r, L, batch, st));
     }
     if (!inv) {
         CT_LAUNCH("pad_fold", 4.0 * batch * (double(RC) + double(g.H) * g.W),
-                  launch_pad_fold(CView{A, RC, g.C}, g.R, g.C,
+                  launch_pad_fold(CView{D, RC, g.C}, g.R, g.C,
                                   View{planes, int64_t(g.H) * g.W, g.W}, g.H, g.W, batch, st));
     }
     return CT_OK;

@@ -73,7 +73,9 @@ __device__ __forceinline__ void step_diag(float (*T)[QLD], int par, float coef, 
 __global__ __launch_bounds__(NT) void dfb12_analysis_kernel(CView d, int R, int C, Quad out,
                                                             Lift L) {
     __shared__ float T[QN][QLD];
-    const int n0 = blockIdx.y * QT, m0 = blockIdx.x * QT, b = blockIdx.z;
+    const int gx = (C + QT - 1) / QT, gy = (R + QT - 1) / QT;
+    const int Lt = xcd_remap(blockIdx.x, gridDim.x);
+    const int n0 = ((Lt / gx) % gy) * QT, m0 = (Lt % gx) * QT, b = Lt / (gx * gy);
     const float* dp = d.p + b * d.plane;
     for (int idx = threadIdx.x; idx < QN * QN; idx += NT) {
         const int r = idx / QN, c = idx - r * QN;
@@ -115,7 +117,9 @@ __global__ __launch_bounds__(NT) void dfb12_analysis_kernel(CView d, int R, int 
 __global__ __launch_bounds__(NT) void dfb12_synthesis_kernel(Quad in, int R, int C, View d,
                                                              Lift L) {
     __shared__ float T[QN][QLD];
-    const int n0 = blockIdx.y * QT, m0 = blockIdx.x * QT, b = blockIdx.z;
+    const int gx = (C + QT - 1) / QT, gy = (R + QT - 1) / QT;
+    const int Lt = xcd_remap(blockIdx.x, gridDim.x);
+    const int n0 = ((Lt / gx) % gy) * QT, m0 = (Lt % gx) * QT, b = Lt / (gx * gy);
     const int Rh = R >> 1, Ch = C >> 1;
     constexpr int HN = QN / 2;   // 40 compact samples per axis
     // horizontal channels (row major): lanes run along compact columns
@@ -160,6 +164,14 @@ constexpr int SN_R = ST_R + 2 * SH;    // 40
 constexpr int SN_C = ST_C + 2 * SH;    // 72
 constexpr int SLD = SN_C + 1;
 
+// Tiles of one horizontal and one vertical parent channel at tree level t.
+__device__ __forceinline__ void split_tile_counts(const SplitArgs& A, int& th, int& tv) {
+    const int t = A.t;
+    auto tiles = [](int nr, int nc) { return ((nr + ST_R - 1) / ST_R) * ((nc + ST_C - 1) / ST_C); };
+    th = tiles(A.Rj >> (t - 2), A.Cj >> 1);
+    tv = tiles(A.Cj >> (t - 2), A.Rj >> 1);
+}
+
 struct SplitGeom {
     int nr, nc;             // parent array size
     int a;                  // shear parameter
@@ -198,6 +210,26 @@ __device__ __forceinline__ SplitGeom split_geom(const SplitArgs& A, int pp) {
     return g;
 }
 
+// Logical block -> (parent channel, tile within it, plane). Per plane the
+// horizontal parents come first, each with th tiles, then the vertical ones.
+__device__ __forceinline__ void split_decode(const SplitArgs& A, int L, int& pp, int& tile, int& b) {
+    int th, tv;
+    split_tile_counts(A, th, tv);
+    const int nh = 1 << (A.t - 2);
+    const int per_plane = nh * (th + tv);
+    b = L / per_plane;
+    int rem = L - b * per_plane;
+    if (rem < nh * th) {
+        pp = rem / th;
+        tile = rem - pp * th;
+    } else {
+        rem -= nh * th;
+        const int v = rem / tv;
+        pp = nh + v;
+        tile = rem - v * tv;
+    }
+}
+
 // Lifting step on rows of parity `par` in the sheared tile, rows/cols [m, N - m).
 __device__ __forceinline__ void step_shear(float (*Q)[SLD], int par, float coef, int m) {
     const int rows = (SN_R - 2 * m) / 2;   // rows of the given parity
@@ -212,10 +244,11 @@ __device__ __forceinline__ void step_shear(float (*Q)[SLD], int par, float coef,
 
 __global__ __launch_bounds__(NT) void split_analysis_kernel(SplitArgs A, Lift L) {
     __shared__ float Q[SN_R][SLD];
-    const SplitGeom g = split_geom(A, blockIdx.y);
-    const int tr = blockIdx.x / g.ctiles, tc = blockIdx.x - tr * g.ctiles;
-    if (tr >= g.rtiles) return;
-    const int r0 = tr * ST_R, k0 = tc * ST_C, b = blockIdx.z;
+    int pp, tile, b;
+    split_decode(A, xcd_remap(blockIdx.x, gridDim.x), pp, tile, b);
+    const SplitGeom g = split_geom(A, pp);
+    const int tr = tile / g.ctiles, tc = tile - tr * g.ctiles;
+    const int r0 = tr * ST_R, k0 = tc * ST_C;
     const float* P = A.parent + b * A.parent_plane + g.parent_off;
     for (int idx = threadIdx.x; idx < SN_R * SN_C; idx += NT) {
         const int r = idx / SN_C, c = idx - r * SN_C;
@@ -247,10 +280,11 @@ __global__ __launch_bounds__(NT) void split_analysis_kernel(SplitArgs A, Lift L)
 
 __global__ __launch_bounds__(NT) void split_synthesis_kernel(SplitArgs A, Lift L) {
     __shared__ float Q[SN_R][SLD];
-    const SplitGeom g = split_geom(A, blockIdx.y);
-    const int tr = blockIdx.x / g.ctiles, tc = blockIdx.x - tr * g.ctiles;
-    if (tr >= g.rtiles) return;
-    const int r0 = tr * ST_R, k0 = tc * ST_C, b = blockIdx.z;
+    int pp, tile, b;
+    split_decode(A, xcd_remap(blockIdx.x, gridDim.x), pp, tile, b);
+    const SplitGeom g = split_geom(A, pp);
+    const int tr = tile / g.ctiles, tc = tile - tr * g.ctiles;
+    const int r0 = tr * ST_R, k0 = tc * ST_C;
     // here `parent` points at the children (input) and `child` at the parent (output)
     const float* ce = A.parent + b * A.parent_plane + g.even_off;
     const float* co = A.parent + b * A.parent_plane + g.odd_off;
@@ -279,40 +313,204 @@ __global__ __launch_bounds__(NT) void split_synthesis_kernel(SplitArgs A, Lift L
     }
 }
 
+// ---------------------------------------------------------------- split pair
+// Two consecutive tree levels t and t+1 in one pass, in the sheared frame Q of
+// the level-(t-1) parent. After the level-t split the even child (rows
+// i = 2i') and the odd child (i = 2i' + 1) live in their own sheared frames
+//   even: Q'[i', k'] = Q[2i', k' - i']     odd: Q'[i', k'] = Q[2i' + 1, k' + a]
+// so their level-(t+1) neighbourhoods, written in Q, are
+//   even rows: N = Q[i-2][k+2] + Q[i+2][k-2] - Q[i-2][k+1] - Q[i+2][k-1]
+//   odd rows:  N = Q[i-2][k+1] + Q[i+2][k-1] - Q[i-2][k]   - Q[i+2][k]
+// (halved), and the sub-parity of row i in its child is (i >> 1) & 1. The four
+// grandchildren are the rows i = 0, 1, 2, 3 (mod 4); every sample keeps the
+// parent's natural column k - a i. A 64 x 64 tile needs a 12-row,
+// 12-column halo: 4 for level t and 8 for level t+1.
+constexpr int PT = 64, PH = 12;
+constexpr int PN = PT + 2 * PH;     // 88
+constexpr int PLD = PN + 1;
+
+__device__ __forceinline__ void step_pair_first(float (*Q)[PLD], int par, float coef, int m) {
+    const int rows = (PN - 2 * m) / 2, cols = PN - 2 * m;
+    const int first = m + ((m + par) & 1);
+    for (int idx = threadIdx.x; idx < rows * cols; idx += NT) {
+        const int rr = idx / cols, cc = idx - rr * cols;
+        const int r = first + 2 * rr, c = m + cc;
+        Q[r][c] += coef * ((Q[r - 1][c + 1] + Q[r + 1][c - 1]) - (Q[r - 1][c] + Q[r + 1][c]));
+    }
+}
+
+// rows with (r >> 1) & 1 == par in [m, PN - m); m even
+__device__ __forceinline__ void step_pair_second(float (*Q)[PLD], int par, float coef, int m) {
+    const int rows = (PN - 2 * m) / 2, cols = PN - 2 * m;
+    const int first = m + ((((m >> 1) & 1) == par) ? 0 : 2);
+    for (int idx = threadIdx.x; idx < rows * cols; idx += NT) {
+        const int rr = idx / cols, cc = idx - rr * cols;
+        const int r = first + 4 * (rr >> 1) + (rr & 1), c = m + cc;
+        const int e = (~r) & 1;    // 1 for the even child: extra column shift
+        Q[r][c] += coef * ((Q[r - 2][c + 1 + e] + Q[r + 2][c - 1 - e]) -
+                           (Q[r - 2][c + e] + Q[r + 2][c - e]));
+    }
+}
+
+// Channel position of grandchild (row class i & 3) of parent pp.
+__device__ __forceinline__ int grandchild_pos(bool vertical, int pp, int cls) {
+    // horizontal: even child = 2pp+1 (its even/odd children 4pp+3 / 4pp+2),
+    //             odd child  = 2pp   (its even/odd children 4pp+1 / 4pp)
+    // vertical:   even child = 2pp   (4pp / 4pp+1), odd child = 2pp+1 (4pp+2 / 4pp+3)
+    const int h = (cls & 1) ? 1 - (cls >> 1) : 3 - (cls >> 1);   // 3, 1, 2, 0
+    const int v = ((cls & 1) << 1) | (cls >> 1);                 // 0, 2, 1, 3
+    return 4 * pp + (vertical ? v : h);
+}
+
+__device__ __forceinline__ void pair_decode(const SplitArgs& A, int L, int& pp, int& tile, int& b,
+                                            int& ctiles) {
+    const int t = A.t;
+    auto cnt = [](int nr, int nc, int& ct) {
+        ct = (nc + PT - 1) / PT;
+        return ((nr + PT - 1) / PT) * ct;
+    };
+    int cth, ctv;
+    const int th = cnt(A.Rj >> (t - 2), A.Cj >> 1, cth);
+    const int tv = cnt(A.Cj >> (t - 2), A.Rj >> 1, ctv);
+    const int nh = 1 << (t - 2);
+    const int per_plane = nh * (th + tv);
+    b = L / per_plane;
+    int rem = L - b * per_plane;
+    if (rem < nh * th) {
+        pp = rem / th;
+        tile = rem - pp * th;
+        ctiles = cth;
+    } else {
+        rem -= nh * th;
+        const int v = rem / tv;
+        pp = nh + v;
+        tile = rem - v * tv;
+        ctiles = ctv;
+    }
+}
+
+__global__ __launch_bounds__(NT) void split2_analysis_kernel(SplitArgs A, Lift L) {
+    __shared__ float Q[PN][PLD];
+    int pp, tile, b, ctiles;
+    pair_decode(A, xcd_remap(blockIdx.x, gridDim.x), pp, tile, b, ctiles);
+    const SplitGeom g = split_geom(A, pp);
+    const bool vertical = pp >= (1 << (A.t - 2));
+    const int r0 = (tile / ctiles) * PT, k0 = (tile % ctiles) * PT;
+    const float* P = A.parent + b * A.parent_plane + g.parent_off;
+    for (int idx = threadIdx.x; idx < PN * PN; idx += NT) {
+        const int r = idx / PN, c = idx - r * PN;
+        const int i = r0 - PH + r, k = k0 - PH + c;
+        Q[r][c] = P[int64_t(wrap(i, g.nr)) * g.nc + wrap(k - g.a * i, g.nc)];
+    }
+    __syncthreads();
+    for (int s = 0; s < 4; ++s) {
+        step_pair_first(Q, (L.first_odd + s) & 1, 0.5f * L.c[s], s + 1);
+        __syncthreads();
+    }
+    for (int s = 0; s < 4; ++s) {
+        step_pair_second(Q, (L.first_odd + s) & 1, 0.5f * L.c[s], 6 + 2 * s);
+        __syncthreads();
+    }
+    const int64_t gsize = A.plane_elems >> (A.t + 1);
+    float* out = A.child + b * A.child_plane;
+    for (int idx = threadIdx.x; idx < PT * PT; idx += NT) {
+        const int r = idx / PT, c = idx - r * PT;
+        const int i = r0 + r, k = k0 + c;
+        if (i >= g.nr || k >= g.nc) continue;
+        const int pos = grandchild_pos(vertical, pp, i & 3);
+        const float sc = A.use_scale ? A.scale[pos] : 1.f;
+        out[pos * gsize + int64_t(i >> 2) * g.nc + wrap(k - g.a * i, g.nc)] = sc * Q[PH + r][PH + c];
+    }
+}
+
+__global__ __launch_bounds__(NT) void split2_synthesis_kernel(SplitArgs A, Lift L) {
+    __shared__ float Q[PN][PLD];
+    int pp, tile, b, ctiles;
+    pair_decode(A, xcd_remap(blockIdx.x, gridDim.x), pp, tile, b, ctiles);
+    const SplitGeom g = split_geom(A, pp);
+    const bool vertical = pp >= (1 << (A.t - 2));
+    const int r0 = (tile / ctiles) * PT, k0 = (tile % ctiles) * PT;
+    // `parent` holds the grandchildren (input), `child` the parent (output)
+    const int64_t gsize = A.plane_elems >> (A.t + 1);
+    const float* in = A.parent + b * A.parent_plane;
+    for (int idx = threadIdx.x; idx < PN * PN; idx += NT) {
+        const int r = idx / PN, c = idx - r * PN;
+        const int i = r0 - PH + r, k = k0 - PH + c;
+        const int ii = wrap(i, g.nr);
+        const int pos = grandchild_pos(vertical, pp, ii & 3);
+        const float sc = A.use_scale ? A.scale[pos] : 1.f;
+        Q[r][c] = sc * in[pos * gsize + int64_t(ii >> 2) * g.nc + wrap(k - g.a * i, g.nc)];
+    }
+    __syncthreads();
+    for (int s = 0; s < 4; ++s) {
+        step_pair_second(Q, (L.first_odd + s) & 1, 0.5f * L.c[s], 2 + 2 * s);
+        __syncthreads();
+    }
+    for (int s = 0; s < 4; ++s) {
+        step_pair_first(Q, (L.first_odd + s) & 1, 0.5f * L.c[s], 9 + s);
+        __syncthreads();
+    }
+    float* P = A.child + b * A.child_plane + g.parent_off;
+    for (int idx = threadIdx.x; idx < PT * PT; idx += NT) {
+        const int r = idx / PT, c = idx - r * PT;
+        const int i = r0 + r, k = k0 + c;
+        if (i >= g.nr || k >= g.nc) continue;
+        P[int64_t(i) * g.nc + wrap(k - g.a * i, g.nc)] = Q[PH + r][PH + c];
+    }
+}
+
 }  // namespace
 
 hipError_t launch_dfb12_analysis(CView d, int R, int C, Quad out, Lift lift, int batch,
                                  hipStream_t st) {
-    dim3 grid((C + QT - 1) / QT, (R + QT - 1) / QT, batch);
+    dim3 grid(((C + QT - 1) / QT) * ((R + QT - 1) / QT) * batch);
     dfb12_analysis_kernel<<<grid, NT, 0, st>>>(d, R, C, out, lift);
     return hipGetLastError();
 }
 
 hipError_t launch_dfb12_synthesis(Quad in, int R, int C, View d, Lift lift, int batch,
                                   hipStream_t st) {
-    dim3 grid((C + QT - 1) / QT, (R + QT - 1) / QT, batch);
+    dim3 grid(((C + QT - 1) / QT) * ((R + QT - 1) / QT) * batch);
     dfb12_synthesis_kernel<<<grid, NT, 0, st>>>(in, R, C, d, lift);
     return hipGetLastError();
 }
 
-static int split_tiles(const SplitArgs& a) {
+static int split_blocks(const SplitArgs& a, int batch) {
     // horizontal parents: (Rj >> (t-2)) x (Cj/2); vertical: (Cj >> (t-2)) x (Rj/2)
     const int t = a.t;
     auto tiles = [](int nr, int nc) { return ((nr + ST_R - 1) / ST_R) * ((nc + ST_C - 1) / ST_C); };
     const int th = tiles(a.Rj >> (t - 2), a.Cj >> 1);
     const int tv = tiles(a.Cj >> (t - 2), a.Rj >> 1);
-    return th > tv ? th : tv;
+    return (1 << (t - 2)) * (th + tv) * batch;
 }
 
 hipError_t launch_dfb_split_analysis(const SplitArgs& a, Lift lift, int batch, hipStream_t st) {
-    dim3 grid(split_tiles(a), 1 << (a.t - 1), batch);
+    dim3 grid(split_blocks(a, batch));
     split_analysis_kernel<<<grid, NT, 0, st>>>(a, lift);
     return hipGetLastError();
 }
 
 hipError_t launch_dfb_split_synthesis(const SplitArgs& a, Lift lift, int batch, hipStream_t st) {
-    dim3 grid(split_tiles(a), 1 << (a.t - 1), batch);
+    dim3 grid(split_blocks(a, batch));
     split_synthesis_kernel<<<grid, NT, 0, st>>>(a, lift);
+    return hipGetLastError();
+}
+
+static int pair_blocks(const SplitArgs& a, int batch) {
+    const int t = a.t;
+    auto tiles = [](int nr, int nc) { return ((nr + PT - 1) / PT) * ((nc + PT - 1) / PT); };
+    const int th = tiles(a.Rj >> (t - 2), a.Cj >> 1);
+    const int tv = tiles(a.Cj >> (t - 2), a.Rj >> 1);
+    return (1 << (t - 2)) * (th + tv) * batch;
+}
+
+hipError_t launch_dfb_split2_analysis(const SplitArgs& a, Lift lift, int batch, hipStream_t st) {
+    split2_analysis_kernel<<<dim3(pair_blocks(a, batch)), NT, 0, st>>>(a, lift);
+    return hipGetLastError();
+}
+
+hipError_t launch_dfb_split2_synthesis(const SplitArgs& a, Lift lift, int batch, hipStream_t st) {
+    split2_synthesis_kernel<<<dim3(pair_blocks(a, batch)), NT, 0, st>>>(a, lift);
     return hipGetLastError();
 }
 

@@ -6,6 +6,17 @@
 
 namespace ct {
 
+// Workgroups are dispatched round-robin over the 8 XCDs of MI355X, each with
+// its own L2. This maps the hardware workgroup id to a logical tile index so
+// that every XCD receives one contiguous range of tiles: neighbouring tiles,
+// which share halo rows and columns, then meet in the same L2.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_remap(int bid, int total) {
+    const int x = bid % kNumXcd, slot = bid / kNumXcd;
+    const int base = total / kNumXcd, rem = total % kNumXcd;
+    return x * base + (x < rem ? x : rem) + slot;
+}
+
 // One-sided taps of a symmetric filter: t[0] centre, t[k] = tap at +-k.
 struct Taps5 {
     float t[5];
@@ -79,6 +90,23 @@ struct SplitArgs {
 };
 hipError_t launch_dfb_split_analysis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
 hipError_t launch_dfb_split_synthesis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
+
+// Tree levels t and t+1 in one pass: parents at level t-1 -> grandchildren
+// at level t+1 (stored back to back in subband order), and back.
+hipError_t launch_dfb_split2_analysis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
+hipError_t launch_dfb_split2_synthesis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
+
+// Fused LP level + DFB tree levels 1-2 (64 x 64 tiles, 16-pixel halo).
+// Analysis: src (c_{j-1}, or the frame on level 1 with pad_mode) -> c_out
+// (the lowpass c_j) and the four tree-level-2 channels `out`.
+hipError_t launch_lp_dfb12_analysis(CView src, int src_h, int src_w, int pad_mode, int R, int C,
+                                    View c_out, Quad out, Taps5 lo, int lo_r, Taps5 up, int up_r,
+                                    Lift lift, int batch, hipStream_t s);
+// Synthesis: the four channels `in` and the lowpass c_in -> x_out (rows <
+// out_h, cols < out_w of the R x C result).
+hipError_t launch_dfb12_lp_synthesis(Quad in, CView c_in, int R, int C, View x_out, int out_h,
+                                     int out_w, Taps5 lo, int lo_r, Taps5 up, int up_r, Lift lift,
+                                     int batch, hipStream_t s);
 
 // Folds the mirrored padding back onto its sources (transpose of padding):
 // out[r][c] = sum of in[r'][c'] over r' in {r, 2H-1-r}, c' in {c, 2W-1-c}

@@ -101,8 +101,10 @@ __global__ __launch_bounds__(NT) void lp_analysis_kernel(CView src, int src_h, i
                                                          int pad_mode, int R, int C, View c_out,
                                                          View d_out, Taps5 lo, Taps5 up) {
     __shared__ LpSmem s;
-    const int n0 = blockIdx.y * TH, m0 = blockIdx.x * TW;
-    const int b = blockIdx.z;
+    const int gx = (C + TW - 1) / TW, gy = (R + TH - 1) / TH;
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = L % gx, ty = (L / gx) % gy, b = L / (gx * gy);
+    const int n0 = ty * TH, m0 = tx * TW;
     const float* sp = src.p + b * src.plane;
     for (int idx = threadIdx.x; idx < IN_R * IN_C; idx += NT) {
         const int r = idx / IN_C, c = idx - r * IN_C;
@@ -150,8 +152,10 @@ __global__ __launch_bounds__(NT) void lp_synthesis_kernel(CView c_in, CView d_in
                                                           View x_out, int out_h, int out_w,
                                                           Taps5 lo, Taps5 up) {
     __shared__ LpSmem s;
-    const int n0 = blockIdx.y * TH, m0 = blockIdx.x * TW;
-    const int b = blockIdx.z;
+    const int gx = (C + TW - 1) / TW, gy = (R + TH - 1) / TH;
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = L % gx, ty = (L / gx) % gy, b = L / (gx * gy);
+    const int n0 = ty * TH, m0 = tx * TW;
     const float* dp = d_in.p + b * d_in.plane;
     for (int idx = threadIdx.x; idx < IN_R * IN_C; idx += NT) {
         const int r = idx / IN_C, c = idx - r * IN_C;
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(NT) void pad_fold_kernel(CView in, int R, int C, Vi
 hipError_t launch_lp_analysis(CView src, int src_h, int src_w, int pad_mode, int R, int C,
                               View c_out, View d_out, Taps5 lo, int lo_r, Taps5 up, int up_r,
                               int batch, hipStream_t st) {
-    dim3 grid((C + TW - 1) / TW, (R + TH - 1) / TH, batch);
+    dim3 grid(((C + TW - 1) / TW) * ((R + TH - 1) / TH) * batch);
     if (lo_r == 4 && up_r == 3)
         lp_analysis_kernel<4, 3><<<grid, NT, 0, st>>>(src, src_h, src_w, pad_mode, R, C, c_out,
                                                       d_out, lo, up);
@@ -221,7 +225,7 @@ hipError_t launch_lp_analysis(CView src, int src_h, int src_w, int pad_mode, int
 hipError_t launch_lp_synthesis(CView c_in, CView d_in, int R, int C, View x_out, int out_h,
                                int out_w, Taps5 lo, int lo_r, Taps5 up, int up_r, int batch,
                                hipStream_t st) {
-    dim3 grid((C + TW - 1) / TW, (R + TH - 1) / TH, batch);
+    dim3 grid(((C + TW - 1) / TW) * ((R + TH - 1) / TH) * batch);
     if (lo_r == 4 && up_r == 3)
         lp_synthesis_kernel<4, 3><<<grid, NT, 0, st>>>(c_in, d_in, R, C, x_out, out_h, out_w, lo,
                                                        up);

@@ -116,22 +116,32 @@ __global__ __launch_bounds__(NT) void quantize_kernel(QuantArgs A) {
     const float* c = A.coeffs + b * A.ncoef;
     int16_t* q = A.idx + b * A.ncoef;
     const float* steps = A.steps + int64_t(b) * A.steps_stride;
-    int64_t e = e0 + threadIdx.x;
-    if (e >= A.ncoef) return;
-    int s = find_subband(A, e);
+    const int64_t e_first = e0 + threadIdx.x;
+    if (e_first >= A.ncoef) return;
+    // issue every load of this thread before any arithmetic (memory-level parallelism)
+    float xs[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int64_t e = e_first + int64_t(it) * NT;
+        xs[it] = e < A.ncoef ? c[e] : 0.f;
+    }
+    int s = find_subband(A, e_first);
+    int64_t next = A.sub_off[s + 1];
     float step = steps[s];
-    for (int it = 0; it < ITEMS; ++it, e += NT) {
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int64_t e = e_first + int64_t(it) * NT;
         if (e >= A.ncoef) break;
-        while (e >= A.sub_off[s + 1]) {
+        while (e >= next) {
             ++s;
+            next = A.sub_off[s + 1];
             step = steps[s];
         }
-        const float x = c[e];
         float v;
         if (s == 0)
-            v = __fdiv_rn(__fmul_rn(__fsub_rn(x, mn), sc), step);
+            v = __fdiv_rn(__fmul_rn(__fsub_rn(xs[it], mn), sc), step);
         else
-            v = __fdiv_rn(x, step);
+            v = __fdiv_rn(xs[it], step);
         q[e] = to_index(v);
     }
 }
@@ -144,17 +154,27 @@ __global__ __launch_bounds__(NT) void dequantize_kernel(QuantArgs A) {
     const int16_t* q = A.idx_in + b * A.ncoef;
     float* out = A.coeffs_out + b * A.ncoef;
     const float* steps = A.steps + int64_t(b) * A.steps_stride;
-    int64_t e = e0 + threadIdx.x;
-    if (e >= A.ncoef) return;
-    int s = find_subband(A, e);
+    const int64_t e_first = e0 + threadIdx.x;
+    if (e_first >= A.ncoef) return;
+    int16_t qs[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int64_t e = e_first + int64_t(it) * NT;
+        qs[it] = e < A.ncoef ? q[e] : int16_t(0);
+    }
+    int s = find_subband(A, e_first);
+    int64_t next = A.sub_off[s + 1];
     float step = steps[s];
-    for (int it = 0; it < ITEMS; ++it, e += NT) {
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int64_t e = e_first + int64_t(it) * NT;
         if (e >= A.ncoef) break;
-        while (e >= A.sub_off[s + 1]) {
+        while (e >= next) {
             ++s;
+            next = A.sub_off[s + 1];
             step = steps[s];
         }
-        const float w = __fmul_rn((float)q[e], step);
+        const float w = __fmul_rn((float)qs[it], step);
         out[e] = (s == 0) ? __fadd_rn(mn, __fmul_rn(w, r)) : w;
     }
 }
