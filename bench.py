@@ -27,13 +27,18 @@ H, W, J, DIRS = 1080, 1920, 4, [32, 16, 8, 8]
 FRAMES = 16
 PLANES = 3 * FRAMES
 
+# kernel -> sources whose text defines it (a change invalidates its counters)
 KERNEL_SOURCES = {
-    "lp_analysis": "ct_lp.hip", "lp_synthesis": "ct_lp.hip", "pad_fold": "ct_lp.hip",
-    "dfb12_analysis": "ct_dfb.hip", "dfb12_synthesis": "ct_dfb.hip",
-    "dfb_split_analysis": "ct_dfb.hip", "dfb_split_synthesis": "ct_dfb.hip",
-    "lowpass_partial": "ct_quant.hip", "quantize": "ct_quant.hip", "dequantize": "ct_quant.hip",
-    "lp_dfb12_analysis": "ct_level.hip", "dfb12_lp_synthesis": "ct_level.hip",
-    "dfb_split2_analysis": "ct_dfb.hip", "dfb_split2_synthesis": "ct_dfb.hip",
+    "lp_dfb12_analysis": ("ct_level.hip", "ct_stages.h", "ct_device.h"),
+    "dfb12_lp_synthesis": ("ct_level.hip", "ct_stages.h", "ct_device.h"),
+    "dfb_split_analysis": ("ct_level.hip", "ct_stages.h", "ct_device.h"),
+    "dfb_split_synthesis": ("ct_level.hip", "ct_stages.h", "ct_device.h"),
+    "dfb_split2_analysis": ("ct_level.hip", "ct_stages.h", "ct_device.h"),
+    "dfb_split2_synthesis": ("ct_level.hip", "ct_stages.h", "ct_device.h"),
+    "pad_fold": ("ct_level.hip",),
+    "lowpass_partial": ("ct_quant.hip",),
+    "quantize": ("ct_quant.hip",),
+    "dequantize": ("ct_quant.hip",),
 }
 
 
@@ -43,9 +48,11 @@ def algorithmic_bytes_per_plane(ncoef):
 
 
 def source_digest(name):
-    path = os.path.join(ROOT, "paper_1510_00561_amd", "csrc", KERNEL_SOURCES[name])
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for fn in KERNEL_SOURCES.get(name, ()):
+        with open(os.path.join(ROOT, "paper_1510_00561_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(name, bytes_per_launch):
@@ -86,6 +93,56 @@ def cpu_baseline(planes_np, steps_np, seconds_budget=30.0):
                       f"in FP64 NumPy, one process ({dt:.1f} s)"}
 
 
+def batched_comparison(steps):
+    """Mixed workload: 64 streams (one YCoCg frame each) of 320x240, 640x480 or
+    1280x720, LP depth 2-4, 8-16 directions, in one persistent graph launch
+    vs the same work as per-stream plain launches."""
+    import numpy as np
+    import torch
+    from paper_1510_00561_amd import ct, synth
+    streams = synth.mixed_streams(64, 4)
+    clips = {}
+    for (h, w) in sorted({(s[0], s[1]) for s in streams}):
+        clips[(h, w)] = synth.clip_planes(8, h, w, 4)
+    rng = synth.rng_for(4)
+    descs = []
+    for i, (h, w, J, dirs) in enumerate(streams):
+        fr = i % 8
+        planes = torch.from_numpy(np.ascontiguousarray(clips[(h, w)][3 * fr:3 * fr + 3])).cuda()
+        nsub = int(ct.layout(h, w, J, dirs)[0].nsub)
+        steps = torch.from_numpy(rng.integers(4, 65, size=(3, nsub)).astype(np.float32)).cuda()
+        descs.append(dict(height=h, width=w, levels=J, dirs=dirs, planes=planes, steps=steps))
+    plan = ct.Batched(descs, graph=True, autotune=True)
+    plan.run()
+    plan.run_plain()
+    torch.cuda.synchronize()
+    ref = [s["out"].clone() for s in plan.streams]
+    plan.run()
+    torch.cuda.synchronize()
+    identical = all(torch.equal(a, s["out"]) for a, s in zip(ref, plan.streams))
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    t_plain = timed(plan.run_plain)
+    t_graph = timed(plan.run)
+    info = plan.info()
+    plan.close()
+    return {"workload": "64 streams (one YCoCg frame each) drawn from 320x240/640x480/1280x720, "
+                        "LP depth 2-4, 8-16 directions, forward+quantise+dequantise+inverse",
+            "t_plain_ms": round(t_plain, 3), "t_batched_graph_ms": round(t_graph, 3),
+            "speedup": round(t_plain / t_graph, 3), "frames_per_s_batched": round(64 / (t_graph / 1e3), 1),
+            "bit_identical_to_plain": identical, "plan": info}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +150,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
                     help="copy: stream 1 GiB through a plain elementwise kernel (counter calibration)")
     args = ap.parse_args()
@@ -178,6 +236,11 @@ def main():
                     "traffic": traffic, "avg_launch_us": round(tms / n * 1e3, 2),
                     "bytes_per_launch": by / n}
 
+    batched = None
+    if not args.no_batched:
+        print("[bench] batched mixed-stream comparison", file=sys.stderr, flush=True)
+        batched = batched_comparison(max(3, args.steps // 2))
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
@@ -199,6 +262,7 @@ def main():
         "wall_s": round(wall, 3),
         "roofline": roofline,
         "kernels": kernels,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

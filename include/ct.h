@@ -180,6 +180,62 @@ int ct_inverse_adjoint(const ct_geom* geom, int32_t batch, const float* gplanes,
                        void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Batched form: many streams of uneven resolution and LP depth run one pass
+ * of the hot path (forward CT, quantise, dequantise, inverse CT) in ONE
+ * persistent launch. Each stream is `batch` planes of one geometry with its
+ * own caller-owned device buffers:
+ *   planes  [batch][H][W] float32 input
+ *   coeffs  [batch][ncoef] float32 forward output
+ *   idx     [batch][ncoef] int16 quantiser indices
+ *   side    [batch][2] float32 lowpass (min, max)
+ *   steps   step table as for ct_quantize (steps_stride 0: one shared row)
+ *   deq     [batch][ncoef] float32 dequantised coefficients
+ *   out     [batch][H][W] float32 reconstruction
+ * ct_plan_create validates every stream, allocates the plan's own workspace,
+ * stage tables and counters (the only device allocations of this library),
+ * and with CT_PLAN_GRAPH captures [counter reset kernel, persistent kernel]
+ * into a HIP graph. With CT_PLAN_AUTOTUNE it times the tile-shape choices of
+ * the deeper DFB levels per level shape (pairs of tree levels on 64 x 64
+ * sheared tiles, or single levels on 32 x 64 tiles) and caches them in a JSON
+ * file (CT_AUTOTUNE_CACHE, default $HOME/.cache/ct_autotune.json).
+ * ct_plan_run enqueues one graph launch (or the two kernels) on `stream`.
+ * ct_plan_run_plain enqueues the same work as separate per-stream,
+ * per-stage launches (the unbatched baseline); both give identical results.
+ * A plan may not run on two streams at once; buffers are read and written
+ * on every run. ct_plan_destroy waits for nothing: synchronise first.
+ */
+typedef struct ct_stream_desc {
+    ct_geom geom;
+    int32_t batch;
+    const float* planes;
+    float* coeffs;
+    int16_t* idx;
+    float* side;
+    const float* steps;
+    int32_t steps_stride;
+    float* deq;
+    float* out;
+} ct_stream_desc;
+
+typedef struct ct_plan ct_plan;
+
+typedef struct ct_plan_info_t {
+    int32_t streams, stages, work_items, workgroups;
+    int32_t graph, autotuned;
+    int32_t levels_paired, levels_single;   /* tile-shape choices of levels with l >= 4 */
+    int64_t workspace_bytes;
+} ct_plan_info_t;
+
+#define CT_PLAN_GRAPH 1
+#define CT_PLAN_AUTOTUNE 2
+
+int ct_plan_create(const ct_stream_desc* streams, int32_t n, int32_t flags, ct_plan** out);
+int ct_plan_run(ct_plan* plan, hipStream_t stream);
+int ct_plan_run_plain(ct_plan* plan, hipStream_t stream);
+int ct_plan_info(const ct_plan* plan, ct_plan_info_t* info);
+void ct_plan_destroy(ct_plan* plan);
+
+/*
  * Per-kernel timing (HIP events), for benchmarks and tracing.
  * ct_profile_enable(1) creates a pool of `max_launches` event pairs (0 picks
  * 16384) and makes every later launch record one event before and one after

@@ -20,10 +20,10 @@ SOURCES = [
     ("ct_geometry.cpp", []),
     ("ct_filters.cpp", []),
     ("ct_api.cpp", []),
-    ("ct_lp.hip", []),
-    ("ct_dfb.hip", []),
+    ("ct_plan.cpp", []),
     ("ct_level.hip", []),
     ("ct_quant.hip", ["-ffp-contract=off"]),
+    ("ct_batched.hip", []),
 ]
 
 COMMON = [

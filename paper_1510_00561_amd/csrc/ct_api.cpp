@@ -20,8 +20,10 @@
 #include <string>
 #include <vector>
 
+#include "ct_batched.h"
 #include "ct_internal.h"
 #include "ct_kernels.h"
+#include "ct_plan_internal.h"
 
 using namespace ct;
 
@@ -78,6 +80,10 @@ bool fault_injected() {
     return f && strcmp(f, "launch") == 0;
 }
 
+}  // namespace
+
+namespace ct {
+
 // ------------------------------------------------------------ profiling
 // Event pairs around launches, recorded only while enabled. The pool is
 // created by ct_profile_enable so that recording never allocates.
@@ -94,43 +100,35 @@ struct Profiler {
     size_t next = 0;
     std::vector<ProfRecord> recs;
 };
-Profiler& profiler() {
+static Profiler& profiler() {
     static Profiler p;
     return p;
 }
 
-struct ProfScope {
-    const char* name;
-    double bytes;
-    hipStream_t st;
-    hipEvent_t a = nullptr, b = nullptr;
-    ProfScope(const char* n, double by, hipStream_t s) : name(n), bytes(by), st(s) {
-        Profiler& p = profiler();
-        std::lock_guard<std::mutex> lock(p.mu);
-        if (!p.on) return;
-        if (p.next + 2 > p.pool.size()) {
-            p.dropped = true;
-            return;
-        }
-        a = p.pool[p.next++];
-        b = p.pool[p.next++];
-        hipEventRecord(a, st);
+ProfScope::ProfScope(const char* n, double by, hipStream_t s) : name(n), bytes(by), st(s) {
+    Profiler& p = profiler();
+    std::lock_guard<std::mutex> lock(p.mu);
+    if (!p.on) return;
+    if (p.next + 2 > p.pool.size()) {
+        p.dropped = true;
+        return;
     }
-    void done() {
-        if (!a) return;
-        Profiler& p = profiler();
-        std::lock_guard<std::mutex> lock(p.mu);
-        hipEventRecord(b, st);
-        p.recs.push_back(ProfRecord{name, bytes, a, b});
-    }
-};
+    a = p.pool[p.next++];
+    b = p.pool[p.next++];
+    hipEventRecord(a, st);
+}
 
-#define CT_LAUNCH(name, bytes, expr)                      \
-    do {                                                  \
-        ProfScope ct_prof_scope_(name, double(bytes), st); \
-        if ((expr) != hipSuccess) return CT_ERR_HIP;      \
-        ct_prof_scope_.done();                            \
-    } while (0)
+void ProfScope::done() {
+    if (!a) return;
+    Profiler& p = profiler();
+    std::lock_guard<std::mutex> lock(p.mu);
+    hipEventRecord(b, st);
+    p.recs.push_back(ProfRecord{name, bytes, a, b});
+}
+
+}  // namespace ct
+
+namespace {
 
 int check_common(const ct_geom* geom, int32_t batch, Geometry* g) {
     if (!geom) return CT_ERR_ARG;
@@ -138,198 +136,271 @@ int check_common(const ct_geom* geom, int32_t batch, Geometry* g) {
     return resolve(geom, g);
 }
 
-// Groups of DFB tree levels >= 3 run per pass: pairs from the top, then a
-// single trailing level when their count is odd.
-int split_groups(int l, int* first, int* count) {
+// Groups of DFB tree levels >= 3 run per pass. grouping 2: pairs from the
+// top, then a single trailing level when their count is odd; grouping 1:
+// one level per pass.
+int split_groups(int l, int grouping, int* first, int* count) {
     int n = 0;
-    for (int t = 3; t <= l; t += 2) {
+    for (int t = 3; t <= l;) {
+        const int c = (grouping == 2 && t + 1 <= l) ? 2 : 1;
         first[n] = t;
-        count[n] = (t + 1 <= l) ? 2 : 1;
+        count[n] = c;
         ++n;
+        t += c;
     }
     return n;
 }
 
-// Analysis direction: image -> coefficients (forward, inverse adjoint).
-int run_analysis(const Geometry& g, int batch, const float* planes, float* coeffs, char* ws,
-                 const Workspace& w, Mode mode, hipStream_t st) {
-    const bool fwd = mode == Mode::Forward;
-    const Taps5 lo = fwd ? taps_h() : taps_g();
-    const Taps5 up = fwd ? taps_g() : taps_h();
-    const int lo_r = fwd ? 4 : 3, up_r = fwd ? 3 : 4;
-    const Lift L = lift_for(mode);
-    const int64_t RC = int64_t(g.R) * g.C;
-    float* A = reinterpret_cast<float*>(ws + w.a_off);
-    float* Bf = reinterpret_cast<float*>(ws + w.b_off);
-    for (int j = 1; j <= g.J; ++j) {
-        const int Rj = g.R >> (j - 1), Cj = g.C >> (j - 1);
-        CView src;
-        int src_h = Rj, src_w = Cj, pad = kPadNone;
-        if (j == 1) {
-            src = CView{planes, int64_t(g.H) * g.W, g.W};
-            src_h = g.H;
-            src_w = g.W;
-            pad = fwd ? kPadReflect : kPadZero;
-        } else {
-            src = CView{reinterpret_cast<const float*>(ws + w.c_off[j - 1]), int64_t(Rj) * Cj, Cj};
-        }
-        View c_out = (j == g.J)
-                         ? View{coeffs, g.ncoef, Cj / 2}
-                         : View{reinterpret_cast<float*>(ws + w.c_off[j]), int64_t(Rj / 2) * (Cj / 2), Cj / 2};
-        const int l = g.l[j - 1];
-        float* level = coeffs + g.level_off[j];
-        const int64_t q4 = int64_t(Rj) * Cj / 4;
-        float sc[kMaxDirs];
-        scale_table(l, fwd ? +1 : -1, sc);
-        Quad quad;
-        if (l == 2) {
-            for (int k = 0; k < 4; ++k) {
-                quad.p[k] = level + k * q4;
-                quad.scale[k] = sc[k];
-            }
-            quad.plane = g.ncoef;
-        } else {
-            for (int k = 0; k < 4; ++k) {
-                quad.p[k] = A + k * q4;
-                quad.scale[k] = 1.f;
-            }
-            quad.plane = RC;
-        }
-        const double lvl_bytes = 8.0 * batch * double(Rj) * Cj;
-        const double lp_bytes = 4.0 * batch *
-            (double(src_h) * src_w + double(Rj / 2) * (Cj / 2) + double(Rj) * Cj);
-        CT_LAUNCH("lp_dfb12_analysis", lp_bytes,
-                  launch_lp_dfb12_analysis(src, src_h, src_w, pad, Rj, Cj, c_out, quad, lo, lo_r,
-                                           up, up_r, L, batch, st));
-        int first[4], count[4];
-        const int ng = split_groups(l, first, count);
-        float* cur = A;
-        float* other = Bf;
-        for (int gi = 0; gi < ng; ++gi) {
-            const bool last = gi == ng - 1;
-            SplitArgs a;
-            memset(&a, 0, sizeof(a));
-            a.t = first[gi];
-            a.Rj = Rj;
-            a.Cj = Cj;
-            a.parent = cur;
-            a.parent_plane = RC;
-            a.plane_elems = int64_t(Rj) * Cj;
-            if (last) {
-                a.child = level;
-                a.child_plane = g.ncoef;
-                a.use_scale = 1;
-                memcpy(a.scale, sc, sizeof(float) * (1 << l));
-            } else {
-                a.child = other;
-                a.child_plane = RC;
-            }
-            if (count[gi] == 2)
-                CT_LAUNCH("dfb_split2_analysis", lvl_bytes, launch_dfb_split2_analysis(a, L, batch, st));
-            else
-                CT_LAUNCH("dfb_split_analysis", lvl_bytes, launch_dfb_split_analysis(a, L, batch, st));
-            float* tmp = cur;
-            cur = other;
-            other = tmp;
-        }
-    }
-    return CT_OK;
-}
+}  // namespace
 
-// Synthesis direction: coefficients -> image (inverse, forward adjoint).
-int run_synthesis(const Geometry& g, int batch, const float* coeffs, float* planes, char* ws,
-                  const Workspace& w, Mode mode, hipStream_t st) {
-    const bool inv = mode == Mode::Inverse;
-    const Taps5 lo = inv ? taps_h() : taps_g();
-    const Taps5 up = inv ? taps_g() : taps_h();
-    const int lo_r = inv ? 4 : 3, up_r = inv ? 3 : 4;
+namespace ct {
+
+// Stage chain of one transform direction (see ct_batched.h). `grouping[j]`
+// selects pairs (2) or single DFB tree levels (1) at LP level j.
+void build_transform_chain(const Geometry& g, int batch, int mode_i, const float* in, float* out,
+                           char* ws, const Workspace& w, const int* grouping,
+                           std::vector<StageDesc>& chain) {
+    const Mode mode = Mode(mode_i);
+    const bool analysis = mode == Mode::Forward || mode == Mode::InverseAdjoint;
+    const bool plain_filters = mode == Mode::Forward || mode == Mode::Inverse;
+    const Taps5 lo = plain_filters ? taps_h() : taps_g();
+    const Taps5 up = plain_filters ? taps_g() : taps_h();
+    const int lo_r = plain_filters ? 4 : 3;
     const Lift L = lift_for(mode);
     const int64_t RC = int64_t(g.R) * g.C;
     float* D = reinterpret_cast<float*>(ws + w.d_off);
     float* A = reinterpret_cast<float*>(ws + w.a_off);
     float* Bf = reinterpret_cast<float*>(ws + w.b_off);
+    auto push = [&](StageDesc d) {
+        d.dep = -1;                        // chains are linked by their user
+        d.batch = batch;
+        d.lift = L;
+        d.lo_r = lo_r;
+        chain.push_back(d);
+    };
+    if (analysis) {
+        float* coeffs = out;
+        for (int j = 1; j <= g.J; ++j) {
+            const int Rj = g.R >> (j - 1), Cj = g.C >> (j - 1);
+            StageDesc d;
+            memset(&d, 0, sizeof(d));
+            d.type = kStLevelAna;
+            stage::LevelAnaArgs& a = d.u.la;
+            if (j == 1) {
+                a.src = CView{in, int64_t(g.H) * g.W, g.W};
+                a.src_h = g.H;
+                a.src_w = g.W;
+                a.pad_mode = mode == Mode::Forward ? kPadReflect : kPadZero;
+            } else {
+                a.src = CView{reinterpret_cast<const float*>(ws + w.c_off[j - 1]), int64_t(Rj) * Cj, Cj};
+                a.src_h = Rj;
+                a.src_w = Cj;
+                a.pad_mode = kPadNone;
+            }
+            a.c_out = (j == g.J)
+                          ? View{coeffs, g.ncoef, Cj / 2}
+                          : View{reinterpret_cast<float*>(ws + w.c_off[j]), int64_t(Rj / 2) * (Cj / 2), Cj / 2};
+            a.R = Rj;
+            a.C = Cj;
+            const int l = g.l[j - 1];
+            float* level = coeffs + g.level_off[j];
+            const int64_t q4 = int64_t(Rj) * Cj / 4;
+            float sc[kMaxDirs];
+            scale_table(l, mode == Mode::Forward ? +1 : -1, sc);
+            for (int k = 0; k < 4; ++k) {
+                a.out.p[k] = (l == 2 ? level : A) + k * q4;
+                a.out.scale[k] = l == 2 ? sc[k] : 1.f;
+            }
+            a.out.plane = l == 2 ? g.ncoef : RC;
+            a.lo = lo;
+            a.up = up;
+            a.L = L;
+            a.batch = batch;
+            d.ntiles = ((Cj + 63) / 64) * ((Rj + 63) / 64) * batch;
+            d.bytes = 4.0 * batch * (double(a.src_h) * a.src_w + double(Rj / 2) * (Cj / 2) + double(Rj) * Cj);
+            push(d);
+            int first[4], count[4];
+            const int ng = split_groups(l, grouping[j - 1], first, count);
+            float* cur = A;
+            float* other = Bf;
+            for (int gi = 0; gi < ng; ++gi) {
+                const bool last = gi == ng - 1;
+                StageDesc e;
+                memset(&e, 0, sizeof(e));
+                e.type = count[gi] == 2 ? kStSplit2Ana : kStSplit1Ana;
+                SplitArgs& sa = e.u.sp;
+                sa.t = first[gi];
+                sa.Rj = Rj;
+                sa.Cj = Cj;
+                sa.parent = cur;
+                sa.parent_plane = RC;
+                sa.plane_elems = int64_t(Rj) * Cj;
+                if (last) {
+                    sa.child = level;
+                    sa.child_plane = g.ncoef;
+                    sa.use_scale = 1;
+                    memcpy(sa.scale, sc, sizeof(float) * (1 << l));
+                } else {
+                    sa.child = other;
+                    sa.child_plane = RC;
+                }
+                e.ntiles = split_stage_tiles(sa, batch, count[gi]);
+                e.bytes = 8.0 * batch * double(Rj) * Cj;
+                push(e);
+                float* tmp = cur;
+                cur = other;
+                other = tmp;
+            }
+        }
+        return;
+    }
+    const float* coeffs = in;
     for (int j = g.J; j >= 1; --j) {
         const int Rj = g.R >> (j - 1), Cj = g.C >> (j - 1);
         const int l = g.l[j - 1];
         const float* level = coeffs + g.level_off[j];
         const int64_t q4 = int64_t(Rj) * Cj / 4;
-        const double lvl_bytes = 8.0 * batch * double(Rj) * Cj;
         float sc[kMaxDirs];
-        scale_table(l, inv ? -1 : +1, sc);
-        Quad quad;
+        scale_table(l, mode == Mode::Inverse ? -1 : +1, sc);
+        StageDesc d;
+        memset(&d, 0, sizeof(d));
+        d.type = kStLevelSyn;
+        stage::LevelSynArgs& a = d.u.ls;
         if (l == 2) {
             for (int k = 0; k < 4; ++k) {
-                quad.p[k] = const_cast<float*>(level) + k * q4;
-                quad.scale[k] = sc[k];
+                a.in.p[k] = const_cast<float*>(level) + k * q4;
+                a.in.scale[k] = sc[k];
             }
-            quad.plane = g.ncoef;
+            a.in.plane = g.ncoef;
         } else {
             int first[4], count[4];
-            const int ng = split_groups(l, first, count);
+            const int ng = split_groups(l, grouping[j - 1], first, count);
             float* cur = A;
             float* other = Bf;
             for (int gi = ng - 1; gi >= 0; --gi) {
-                SplitArgs a;
-                memset(&a, 0, sizeof(a));
-                a.t = first[gi];
-                a.Rj = Rj;
-                a.Cj = Cj;
-                a.plane_elems = int64_t(Rj) * Cj;
-                a.child = cur;            // output: the parents
-                a.child_plane = RC;
+                StageDesc e;
+                memset(&e, 0, sizeof(e));
+                e.type = count[gi] == 2 ? kStSplit2Syn : kStSplit1Syn;
+                SplitArgs& sa = e.u.sp;
+                sa.t = first[gi];
+                sa.Rj = Rj;
+                sa.Cj = Cj;
+                sa.plane_elems = int64_t(Rj) * Cj;
+                sa.child = cur;             // output: the parents
+                sa.child_plane = RC;
                 if (gi == ng - 1) {
-                    a.parent = level;     // input: the final subbands
-                    a.parent_plane = g.ncoef;
-                    a.use_scale = 1;
-                    memcpy(a.scale, sc, sizeof(float) * (1 << l));
+                    sa.parent = level;      // input: the final subbands
+                    sa.parent_plane = g.ncoef;
+                    sa.use_scale = 1;
+                    memcpy(sa.scale, sc, sizeof(float) * (1 << l));
                 } else {
-                    a.parent = other;
-                    a.parent_plane = RC;
+                    sa.parent = other;
+                    sa.parent_plane = RC;
                 }
-                if (count[gi] == 2)
-                    CT_LAUNCH("dfb_split2_synthesis", lvl_bytes,
-                              launch_dfb_split2_synthesis(a, L, batch, st));
-                else
-                    CT_LAUNCH("dfb_split_synthesis", lvl_bytes,
-                              launch_dfb_split_synthesis(a, L, batch, st));
+                e.ntiles = split_stage_tiles(sa, batch, count[gi]);
+                e.bytes = 8.0 * batch * double(Rj) * Cj;
+                push(e);
                 float* tmp = cur;
                 cur = other;
                 other = tmp;
             }
-            // the last pass wrote into `other` (after the swap)
             for (int k = 0; k < 4; ++k) {
-                quad.p[k] = other + k * q4;
-                quad.scale[k] = 1.f;
+                a.in.p[k] = other + k * q4;
+                a.in.scale[k] = 1.f;
             }
-            quad.plane = RC;
+            a.in.plane = RC;
         }
-        CView c_in = (j == g.J)
-                         ? CView{coeffs, g.ncoef, Cj / 2}
-                         : CView{reinterpret_cast<const float*>(ws + w.c_off[j]), int64_t(Rj / 2) * (Cj / 2), Cj / 2};
-        View x_out;
-        int out_h = Rj, out_w = Cj;
-        if (j == 1 && inv) {
-            x_out = View{planes, int64_t(g.H) * g.W, g.W};
-            out_h = g.H;
-            out_w = g.W;
+        a.c_in = (j == g.J)
+                     ? CView{coeffs, g.ncoef, Cj / 2}
+                     : CView{reinterpret_cast<const float*>(ws + w.c_off[j]), int64_t(Rj / 2) * (Cj / 2), Cj / 2};
+        a.R = Rj;
+        a.C = Cj;
+        a.out_h = Rj;
+        a.out_w = Cj;
+        if (j == 1 && mode == Mode::Inverse) {
+            a.x_out = View{out, int64_t(g.H) * g.W, g.W};
+            a.out_h = g.H;
+            a.out_w = g.W;
         } else if (j == 1) {
-            x_out = View{D, RC, g.C};
+            a.x_out = View{D, RC, g.C};
         } else {
-            x_out = View{reinterpret_cast<float*>(ws + w.c_off[j - 1]), int64_t(Rj) * Cj, Cj};
+            a.x_out = View{reinterpret_cast<float*>(ws + w.c_off[j - 1]), int64_t(Rj) * Cj, Cj};
         }
-        const double lps_bytes = 4.0 * batch *
-            (double(Rj / 2) * (Cj / 2) + double(Rj) * Cj + double(out_h) * out_w);
-        CT_LAUNCH("dfb12_lp_synthesis", lps_bytes,
-                  launch_dfb12_lp_synthesis(quad, c_in, Rj, Cj, x_out, out_h, out_w, lo, lo_r, up,
-                                            up_r, L, batch, st));
+        a.lo = lo;
+        a.up = up;
+        a.L = L;
+        a.batch = batch;
+        d.ntiles = ((Cj + 63) / 64) * ((Rj + 63) / 64) * batch;
+        d.bytes = 4.0 * batch * (double(Rj / 2) * (Cj / 2) + double(Rj) * Cj + double(a.out_h) * a.out_w);
+        push(d);
     }
-    if (!inv) {
-        CT_LAUNCH("pad_fold", 4.0 * batch * (double(RC) + double(g.H) * g.W),
-                  launch_pad_fold(CView{D, RC, g.C}, g.R, g.C,
-                                  View{planes, int64_t(g.H) * g.W, g.W}, g.H, g.W, batch, st));
+}
+
+}  // namespace ct
+
+namespace {
+
+const char* stage_name(int type) {
+    switch (type) {
+        case kStLevelAna: return "lp_dfb12_analysis";
+        case kStSplit1Ana: return "dfb_split_analysis";
+        case kStSplit2Ana: return "dfb_split2_analysis";
+        case kStPartial: return "lowpass_partial";
+        case kStQuantize: return "quantize";
+        case kStDequantize: return "dequantize";
+        case kStSplit1Syn: return "dfb_split_synthesis";
+        case kStSplit2Syn: return "dfb_split2_synthesis";
+        case kStLevelSyn: return "dfb12_lp_synthesis";
+        default: return "unknown";
+    }
+}
+
+hipError_t launch_stage_raw(const StageDesc& d, hipStream_t st) {
+    const int up_r = d.lo_r == 4 ? 3 : 4;
+    switch (d.type) {
+        case kStLevelAna: {
+            const stage::LevelAnaArgs& a = d.u.la;
+            return launch_lp_dfb12_analysis(a.src, a.src_h, a.src_w, a.pad_mode, a.R, a.C, a.c_out,
+                                            a.out, a.lo, d.lo_r, a.up, up_r, a.L, d.batch, st);
+        }
+        case kStLevelSyn: {
+            const stage::LevelSynArgs& a = d.u.ls;
+            return launch_dfb12_lp_synthesis(a.in, a.c_in, a.R, a.C, a.x_out, a.out_h, a.out_w,
+                                             a.lo, d.lo_r, a.up, up_r, a.L, d.batch, st);
+        }
+        case kStSplit1Ana: return launch_dfb_split_analysis(d.u.sp, d.lift, d.batch, st);
+        case kStSplit2Ana: return launch_dfb_split2_analysis(d.u.sp, d.lift, d.batch, st);
+        case kStSplit1Syn: return launch_dfb_split_synthesis(d.u.sp, d.lift, d.batch, st);
+        case kStSplit2Syn: return launch_dfb_split2_synthesis(d.u.sp, d.lift, d.batch, st);
+        case kStPartial: return launch_lowpass_partial(d.u.q, d.batch, st);
+        case kStQuantize: return launch_quantize(d.u.q, d.batch, st);
+        case kStDequantize: return launch_dequantize(d.u.q, d.batch, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+namespace ct {
+
+int launch_stage(const StageDesc& d, hipStream_t st) {
+    CT_PROFILED(stage_name(d.type), d.bytes, launch_stage_raw(d, st), st);
+    return CT_OK;
+}
+
+int launch_chain(const std::vector<StageDesc>& chain, hipStream_t st) {
+    for (const StageDesc& d : chain) {
+        const int rc = launch_stage(d, st);
+        if (rc != CT_OK) return rc;
     }
     return CT_OK;
 }
+
+}  // namespace ct
+
+namespace {
+
+const int kDefaultGrouping[kMaxLevels] = {2, 2, 2, 2, 2, 2};
 
 int transform(const ct_geom* geom, int32_t batch, const float* in, float* out, void* ws,
               size_t ws_bytes, hipStream_t st, Mode mode) {
@@ -342,16 +413,30 @@ int transform(const ct_geom* geom, int32_t batch, const float* in, float* out, v
     if (ws_bytes < w.total) return CT_ERR_WORKSPACE;
     if (!constants().ok) return CT_ERR_UNSUPPORTED;
     if (fault_injected()) return CT_ERR_HIP;
-    char* wsb = static_cast<char*>(ws);
-    if (mode == Mode::Forward || mode == Mode::InverseAdjoint)
-        return run_analysis(g, batch, in, out, wsb, w, mode, st);
-    return run_synthesis(g, batch, in, out, wsb, w, mode, st);
+    std::vector<StageDesc> chain;
+    build_transform_chain(g, batch, int(mode), in, out, static_cast<char*>(ws), w,
+                          kDefaultGrouping, chain);
+    rc = launch_chain(chain, st);
+    if (rc != CT_OK) return rc;
+    if (mode == Mode::ForwardAdjoint) {
+        const int64_t RC = int64_t(g.R) * g.C;
+        float* D = reinterpret_cast<float*>(static_cast<char*>(ws) + w.d_off);
+        CT_PROFILED("pad_fold", 4.0 * batch * (double(RC) + double(g.H) * g.W),
+                    launch_pad_fold(CView{D, RC, g.C}, g.R, g.C,
+                                    View{out, int64_t(g.H) * g.W, g.W}, g.H, g.W, batch, st),
+                    st);
+    }
+    return CT_OK;
 }
+
+}  // namespace
+
+namespace ct {
 
 int fill_quant_args(const Geometry& g, QuantArgs* a) {
     if (g.nsub + 1 > int(sizeof(a->sub_off) / sizeof(a->sub_off[0]))) return CT_ERR_GEOM;
-    ct_subband table[400];
-    subband_table(g, table, 400);
+    std::vector<ct_subband> table(g.nsub);
+    subband_table(g, table.data(), g.nsub);
     for (int s = 0; s < g.nsub; ++s) a->sub_off[s] = int(table[s].offset);
     a->sub_off[g.nsub] = int(g.ncoef);
     a->nsub = g.nsub;
@@ -364,7 +449,57 @@ int fill_quant_args(const Geometry& g, QuantArgs* a) {
     return CT_OK;
 }
 
-}  // namespace
+// Quantiser stages: lowpass partials, then the indices.
+int build_quant_chain(const Geometry& g, int batch, const float* coeffs, const float* steps,
+                      int steps_stride, int16_t* idx, float* side, char* ws, const Workspace& w,
+                      std::vector<StageDesc>& chain) {
+    StageDesc d;
+    memset(&d, 0, sizeof(d));
+    int rc = fill_quant_args(g, &d.u.q);
+    if (rc != CT_OK) return rc;
+    QuantArgs& a = d.u.q;
+    a.coeffs = coeffs;
+    a.idx = idx;
+    a.side = side;
+    a.steps = steps;
+    a.steps_stride = steps_stride;
+    a.partials = reinterpret_cast<float*>(ws + w.part_off);
+    d.batch = batch;
+    d.dep = -1;
+    d.type = kStPartial;
+    d.ntiles = a.nparts * batch;
+    d.bytes = 4.0 * batch * double(g.low_n);
+    chain.push_back(d);
+    d.type = kStQuantize;
+    d.ntiles = int((g.ncoef + 4095) / 4096) * batch;
+    d.bytes = 6.0 * batch * double(g.ncoef);
+    chain.push_back(d);
+    return CT_OK;
+}
+
+int build_dequant_chain(const Geometry& g, int batch, const int16_t* idx, const float* steps,
+                        int steps_stride, const float* side, float* coeffs,
+                        std::vector<StageDesc>& chain) {
+    StageDesc d;
+    memset(&d, 0, sizeof(d));
+    int rc = fill_quant_args(g, &d.u.q);
+    if (rc != CT_OK) return rc;
+    QuantArgs& a = d.u.q;
+    a.idx_in = idx;
+    a.coeffs_out = coeffs;
+    a.side = const_cast<float*>(side);
+    a.steps = steps;
+    a.steps_stride = steps_stride;
+    d.batch = batch;
+    d.dep = -1;
+    d.type = kStDequantize;
+    d.ntiles = int((g.ncoef + 4095) / 4096) * batch;
+    d.bytes = 6.0 * batch * double(g.ncoef);
+    chain.push_back(d);
+    return CT_OK;
+}
+
+}  // namespace ct
 
 extern "C" {
 
@@ -425,20 +560,11 @@ int ct_quantize(const ct_geom* geom, int32_t batch, const float* coeffs, const f
     const Workspace w = workspace_layout(g, batch);
     if (ws_bytes < w.total) return CT_ERR_WORKSPACE;
     if (fault_injected()) return CT_ERR_HIP;
-    QuantArgs a;
-    memset(&a, 0, sizeof(a));
-    rc = fill_quant_args(g, &a);
+    std::vector<StageDesc> chain;
+    rc = build_quant_chain(g, batch, coeffs, steps, steps_stride, idx, side,
+                           static_cast<char*>(ws), w, chain);
     if (rc != CT_OK) return rc;
-    a.coeffs = coeffs;
-    a.idx = idx;
-    a.side = side;
-    a.steps = steps;
-    a.steps_stride = steps_stride;
-    a.partials = reinterpret_cast<float*>(static_cast<char*>(ws) + w.part_off);
-    hipStream_t st = stream;
-    CT_LAUNCH("lowpass_partial", 4.0 * batch * double(g.low_n), launch_lowpass_partial(a, batch, st));
-    CT_LAUNCH("quantize", 6.0 * batch * double(g.ncoef), launch_quantize(a, batch, st));
-    return CT_OK;
+    return launch_chain(chain, stream);
 }
 
 int ct_dequantize(const ct_geom* geom, int32_t batch, const int16_t* idx, const float* steps,
@@ -450,18 +576,10 @@ int ct_dequantize(const ct_geom* geom, int32_t batch, const int16_t* idx, const 
     if (!coeffs || !steps || !idx || !side) return CT_ERR_ARG;
     if (steps_stride < 0 || (steps_stride > 0 && steps_stride < g.nsub)) return CT_ERR_ARG;
     if (fault_injected()) return CT_ERR_HIP;
-    QuantArgs a;
-    memset(&a, 0, sizeof(a));
-    rc = fill_quant_args(g, &a);
+    std::vector<StageDesc> chain;
+    rc = build_dequant_chain(g, batch, idx, steps, steps_stride, side, coeffs, chain);
     if (rc != CT_OK) return rc;
-    a.idx_in = idx;
-    a.coeffs_out = coeffs;
-    a.side = const_cast<float*>(side);
-    a.steps = steps;
-    a.steps_stride = steps_stride;
-    hipStream_t st = stream;
-    CT_LAUNCH("dequantize", 6.0 * batch * double(g.ncoef), launch_dequantize(a, batch, st));
-    return CT_OK;
+    return launch_chain(chain, stream);
 }
 
 int ct_profile_enable(int32_t on, int32_t max_launches) {

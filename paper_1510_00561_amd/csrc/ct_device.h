@@ -13,6 +13,16 @@ __device__ __forceinline__ int wrap(int i, int n) {
     return r < 0 ? r + n : r;
 }
 
+// i mod n (non-negative) with a float reciprocal inv = 1/n instead of an
+// integer division: the float quotient is off by at most one for |i| < 2^22,
+// which the two corrections absorb.
+__device__ __forceinline__ int fwrap(int i, int n, float inv) {
+    int r = i - int(floorf(float(i) * inv)) * n;
+    if (r < 0) r += n;
+    if (r >= n) r -= n;
+    return r;
+}
+
 // ---------------------------------------------------------------- LP passes
 // A tile stores its full-resolution input `in` with the lowpass grid aligned
 // so that lowpass sample t (local) sits over input column 4 + 2t, and lowpass
@@ -82,12 +92,21 @@ template <int N, int LD, int NT>
 __device__ __forceinline__ void step_cross(float* T, int par, float coef, int m) {
     const int span = N - 2 * m;
     const int half = span / 2;
-    for (int idx = threadIdx.x; idx < span * half; idx += NT) {
-        const int rr = idx / half, j = idx - rr * half;
+    // (row, half-column) of this thread's first point and the per-iteration
+    // advance, so the loop needs no division per point
+    const int q = NT / half, rmd = NT - q * half;
+    int rr = threadIdx.x / half, j = threadIdx.x - rr * half;
+    while (rr < span) {
         const int r = m + rr;
         const int c = m + 2 * j + ((r + m + par) & 1);
         float* p = T + r * LD + c;
         *p += coef * ((p[1] + p[-1]) - (p[LD] + p[-LD]));
+        rr += q;
+        j += rmd;
+        if (j >= half) {
+            j -= half;
+            ++rr;
+        }
     }
 }
 
@@ -97,12 +116,18 @@ template <int N, int LD, int NT>
 __device__ __forceinline__ void step_diag(float* T, int par, float coef, int m) {
     const int span = N - 2 * m;
     const int half = span / 2;
-    for (int idx = threadIdx.x; idx < span * half; idx += NT) {
-        const int rr = idx / half, j = idx - rr * half;
-        const int r = m + rr;
-        const int c = m + 2 * j + ((m + par) & 1);
-        float* p = T + r * LD + c;
+    const int q = NT / half, rmd = NT - q * half;
+    int rr = threadIdx.x / half, j = threadIdx.x - rr * half;
+    const int c0 = m + ((m + par) & 1);
+    while (rr < span) {
+        float* p = T + (m + rr) * LD + c0 + 2 * j;
         *p += coef * ((p[-LD + 1] + p[LD - 1]) - (p[LD + 1] + p[-LD - 1]));
+        rr += q;
+        j += rmd;
+        if (j >= half) {
+            j -= half;
+            ++rr;
+        }
     }
 }
 

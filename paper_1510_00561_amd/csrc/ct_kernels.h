@@ -45,18 +45,6 @@ struct CView {
 // How the level-1 analysis reads beyond the real frame.
 enum PadMode { kPadNone = 0, kPadReflect = 1, kPadZero = 2 };
 
-// LP analysis level: c = down2(lo * x), d = x - up * up2(c). `lo_r`
-// selects the reach of lo (4 for hbar, 3 for gbar); `up_r` that of up.
-hipError_t launch_lp_analysis(CView src, int src_h, int src_w, int pad_mode, int R, int C,
-                              View c_out, View d_out, Taps5 lo, int lo_r, Taps5 up, int up_r,
-                              int batch, hipStream_t s);
-
-// LP dual synthesis level: c' = c - down2(lo * d), x = d + up * up2(c').
-// Writes rows < out_h and cols < out_w of the R x C result.
-hipError_t launch_lp_synthesis(CView c_in, CView d_in, int R, int C, View x_out, int out_h,
-                               int out_w, Taps5 lo, int lo_r, Taps5 up, int up_r, int batch,
-                               hipStream_t s);
-
 // Output/input description of the four tree-level-2 channels, in subband
 // order: [H a=-1 (coset (0,1)), H a=0 (1,0), V a=0 (0,0), V a=-1 (1,1)].
 // Horizontal channels are (R/2) x (C/2) row major; vertical channels are
@@ -66,13 +54,6 @@ struct Quad {
     int64_t plane;
     float scale[4];
 };
-
-// DFB tree levels 1 and 2 on a level image: analysis (d -> 4 channels) and
-// synthesis (4 channels -> d).
-hipError_t launch_dfb12_analysis(CView d, int R, int C, Quad out, Lift lift, int batch,
-                                 hipStream_t s);
-hipError_t launch_dfb12_synthesis(Quad in, int R, int C, View d, Lift lift, int batch,
-                                  hipStream_t s);
 
 // One DFB tree level t >= 3 for all channels of an LP level whose image is
 // R_j x C_j. Channels of a tree level are stored back to back in subband

@@ -1,0 +1,55 @@
+// Host-side stage-chain builders shared by the plain entry points and the
+// batched plan.
+#pragma once
+
+#include <vector>
+
+#include "ct_batched.h"
+#include "ct_internal.h"
+
+namespace ct {
+
+// Per-launch HIP-event timing (ct_profile_enable): a scope records an event
+// on `st` when constructed and another at done(), only while profiling is on.
+struct ProfScope {
+    const char* name;
+    double bytes;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(const char* n, double by, hipStream_t s);
+    void done();
+};
+
+#define CT_PROFILED(name, bytes, expr, stream)                       \
+    do {                                                             \
+        ::ct::ProfScope ct_prof_scope_(name, double(bytes), stream); \
+        if ((expr) != hipSuccess) return CT_ERR_HIP;                 \
+        ct_prof_scope_.done();                                       \
+    } while (0)
+
+// Transform modes, in the order used by build_transform_chain.
+enum ChainMode { kModeForward = 0, kModeInverse = 1, kModeForwardAdjoint = 2, kModeInverseAdjoint = 3 };
+
+void build_transform_chain(const Geometry& g, int batch, int mode, const float* in, float* out,
+                           char* ws, const Workspace& w, const int* grouping,
+                           std::vector<StageDesc>& chain);
+int build_quant_chain(const Geometry& g, int batch, const float* coeffs, const float* steps,
+                      int steps_stride, int16_t* idx, float* side, char* ws, const Workspace& w,
+                      std::vector<StageDesc>& chain);
+int build_dequant_chain(const Geometry& g, int batch, const int16_t* idx, const float* steps,
+                        int steps_stride, const float* side, float* coeffs,
+                        std::vector<StageDesc>& chain);
+int launch_stage(const StageDesc& d, hipStream_t st);
+int launch_chain(const std::vector<StageDesc>& chain, hipStream_t st);
+int fill_quant_args(const Geometry& g, QuantArgs* a);
+
+// Tiles of a DFB split stage covering `levels` (1 or 2) tree levels.
+inline int split_stage_tiles(const SplitArgs& a, int batch, int levels) {
+    const int tr = levels == 1 ? 32 : 64, tc = 64;
+    const int t = a.t;
+    const int th = (((a.Rj >> (t - 2)) + tr - 1) / tr) * (((a.Cj >> 1) + tc - 1) / tc);
+    const int tv = (((a.Cj >> (t - 2)) + tr - 1) / tr) * (((a.Rj >> 1) + tc - 1) / tc);
+    return (1 << (t - 2)) * (th + tv) * batch;
+}
+
+}  // namespace ct

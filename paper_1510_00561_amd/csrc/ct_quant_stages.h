@@ -1,0 +1,182 @@
+// Quantiser stages (device functions), shared by the quantiser kernels and
+// the batched work-queue kernel. The float32 operation order is part of the
+// contract (ct.h, ct_quantize): every function body disables FMA contraction
+// (the _rn helpers are plain operators in this toolchain configuration).
+//
+// Paper section 3.4 (lowpass normalised to [0, 255], restored at the
+// decoder), section 3.5 (division by QPH / QPL), section 3.6 (rounding to the
+// nearest integer).
+#pragma once
+
+#include <math.h>
+
+#include "ct_internal.h"
+#include "ct_kernels.h"
+
+namespace ct {
+namespace qstage {
+
+constexpr int CHUNK = 4096;     // coefficients per quantiser tile
+
+template <int NT>
+__device__ __forceinline__ void block_minmax(float& mn, float& mx, float* red) {
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = fminf(mn, __shfl_xor(mn, o, 64));
+        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        red[2 * w] = mn;
+        red[2 * w + 1] = mx;
+    }
+    __syncthreads();
+    mn = red[0];
+    mx = red[1];
+    for (int i = 1; i < NT / 64; ++i) {
+        mn = fminf(mn, red[2 * i]);
+        mx = fmaxf(mx, red[2 * i + 1]);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int16_t to_index(float v) {
+    const float r = roundf(v);            // halves away from zero
+    if (!(r == r)) return 0;              // NaN
+    if (r >= 32767.f) return 32767;
+    if (r <= -32768.f) return -32768;
+    return (int16_t)(int)r;
+}
+
+__device__ __forceinline__ int find_subband(const QuantArgs& A, int64_t e) {
+    int lo = 0, hi = A.nsub - 1;           // largest s with sub_off[s] <= e
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.sub_off[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int partial_tiles(const QuantArgs& A, int batch) { return A.nparts * batch; }
+__device__ __forceinline__ int chunk_tiles(const QuantArgs& A, int batch) {
+    return int((A.ncoef + CHUNK - 1) / CHUNK) * batch;
+}
+
+// Pass 1: (min, max) of one block of one plane's lowpass.
+template <int NT>
+__device__ void lowpass_partial(const QuantArgs& A, int tile, float* red) {
+#pragma clang fp contract(off)
+    const int b = tile / A.nparts, p = tile - b * A.nparts;
+    const int64_t per = (A.low_n + A.nparts - 1) / A.nparts;
+    const int64_t lo = p * per;
+    const int64_t hi = lo + per < A.low_n ? lo + per : A.low_n;
+    const float* c = A.coeffs + b * A.ncoef;
+    float mn = INFINITY, mx = -INFINITY;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += NT) {
+        const float v = c[e];
+        mn = fminf(mn, v);
+        mx = fmaxf(mx, v);
+    }
+    block_minmax<NT>(mn, mx, red);
+    if (threadIdx.x == 0) {
+        A.partials[(int64_t(b) * kMaxPart + p) * 2 + 0] = mn;
+        A.partials[(int64_t(b) * kMaxPart + p) * 2 + 1] = mx;
+    }
+}
+
+// Pass 2: indices of one chunk of CHUNK coefficients of one plane.
+template <int NT>
+__device__ void quantize(const QuantArgs& A, int tile, float* red) {
+#pragma clang fp contract(off)
+    constexpr int ITEMS = CHUNK / NT;
+    const int nch = int((A.ncoef + CHUNK - 1) / CHUNK);
+    const int b = tile / nch;
+    const int64_t e0 = int64_t(tile - b * nch) * CHUNK;
+    float mn = 0.f, mx = 0.f, sc = 0.f;
+    if (e0 < A.low_n) {
+        float pmn = INFINITY, pmx = -INFINITY;
+        for (int p = threadIdx.x; p < A.nparts; p += NT) {
+            pmn = fminf(pmn, A.partials[(int64_t(b) * kMaxPart + p) * 2 + 0]);
+            pmx = fmaxf(pmx, A.partials[(int64_t(b) * kMaxPart + p) * 2 + 1]);
+        }
+        block_minmax<NT>(pmn, pmx, red);
+        mn = pmn;
+        mx = pmx;
+        sc = (mx == mn) ? 0.f : __fdiv_rn(255.f, __fsub_rn(mx, mn));
+        if (e0 == 0 && threadIdx.x == 0) {
+            A.side[2 * b + 0] = mn;
+            A.side[2 * b + 1] = mx;
+        }
+    }
+    const float* c = A.coeffs + b * A.ncoef;
+    int16_t* q = A.idx + b * A.ncoef;
+    const float* steps = A.steps + int64_t(b) * A.steps_stride;
+    const int64_t e_first = e0 + threadIdx.x;
+    if (e_first >= A.ncoef) return;
+    float xs[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int64_t e = e_first + int64_t(it) * NT;
+        xs[it] = e < A.ncoef ? c[e] : 0.f;
+    }
+    int s = find_subband(A, e_first);
+    int64_t next = A.sub_off[s + 1];
+    float step = steps[s];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int64_t e = e_first + int64_t(it) * NT;
+        if (e >= A.ncoef) break;
+        while (e >= next) {
+            ++s;
+            next = A.sub_off[s + 1];
+            step = steps[s];
+        }
+        float v;
+        if (s == 0)
+            v = __fdiv_rn(__fmul_rn(__fsub_rn(xs[it], mn), sc), step);
+        else
+            v = __fdiv_rn(xs[it], step);
+        q[e] = to_index(v);
+    }
+}
+
+// Dequantise one chunk.
+template <int NT>
+__device__ void dequantize(const QuantArgs& A, int tile) {
+#pragma clang fp contract(off)
+    constexpr int ITEMS = CHUNK / NT;
+    const int nch = int((A.ncoef + CHUNK - 1) / CHUNK);
+    const int b = tile / nch;
+    const int64_t e0 = int64_t(tile - b * nch) * CHUNK;
+    const float mn = A.side[2 * b + 0], mx = A.side[2 * b + 1];
+    const float r = __fdiv_rn(__fsub_rn(mx, mn), 255.f);
+    const int16_t* q = A.idx_in + b * A.ncoef;
+    float* out = A.coeffs_out + b * A.ncoef;
+    const float* steps = A.steps + int64_t(b) * A.steps_stride;
+    const int64_t e_first = e0 + threadIdx.x;
+    if (e_first >= A.ncoef) return;
+    int16_t qs[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int64_t e = e_first + int64_t(it) * NT;
+        qs[it] = e < A.ncoef ? q[e] : int16_t(0);
+    }
+    int s = find_subband(A, e_first);
+    int64_t next = A.sub_off[s + 1];
+    float step = steps[s];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int64_t e = e_first + int64_t(it) * NT;
+        if (e >= A.ncoef) break;
+        while (e >= next) {
+            ++s;
+            next = A.sub_off[s + 1];
+            step = steps[s];
+        }
+        const float w = __fmul_rn((float)qs[it], step);
+        out[e] = (s == 0) ? __fadd_rn(mn, __fmul_rn(w, r)) : w;
+    }
+}
+
+}  // namespace qstage
+}  // namespace ct

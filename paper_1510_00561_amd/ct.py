@@ -46,6 +46,26 @@ class KernelStat(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+class StreamDesc(ctypes.Structure):
+    _fields_ = [("geom", Geom), ("batch", ctypes.c_int32),
+                ("planes", ctypes.c_void_p), ("coeffs", ctypes.c_void_p),
+                ("idx", ctypes.c_void_p), ("side", ctypes.c_void_p),
+                ("steps", ctypes.c_void_p), ("steps_stride", ctypes.c_int32),
+                ("deq", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_int32), ("stages", ctypes.c_int32),
+                ("work_items", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("autotuned", ctypes.c_int32),
+                ("levels_paired", ctypes.c_int32), ("levels_single", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_int64)]
+
+
+PLAN_GRAPH = 1
+PLAN_AUTOTUNE = 2
+
+
 class CTError(RuntimeError):
     def __init__(self, fn, code):
         super().__init__(f"{fn} failed: {ERRORS.get(code, code)} ({_lib().ct_strerror(code).decode()})")
@@ -83,6 +103,15 @@ def _lib():
         lib.ct_profile_enable.restype = ctypes.c_int
         lib.ct_profile_collect.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
         lib.ct_profile_collect.restype = ctypes.c_int
+        lib.ct_plan_create.argtypes = [ctypes.POINTER(StreamDesc), i32, i32, ctypes.POINTER(ctypes.c_void_p)]
+        lib.ct_plan_create.restype = ctypes.c_int
+        for name in ("ct_plan_run", "ct_plan_run_plain"):
+            getattr(lib, name).argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+            getattr(lib, name).restype = ctypes.c_int
+        lib.ct_plan_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(PlanInfo)]
+        lib.ct_plan_info.restype = ctypes.c_int
+        lib.ct_plan_destroy.argtypes = [ctypes.c_void_p]
+        lib.ct_plan_destroy.restype = None
         lib.ct_strerror.argtypes = [ctypes.c_int]
         lib.ct_strerror.restype = ctypes.c_char_p
         _LIB = lib
@@ -237,3 +266,76 @@ def forward(x, levels, dirs):
 def inverse(coeffs, height, width, levels, dirs):
     B = coeffs.shape[0]
     return Plan(height, width, levels, dirs, B, coeffs.device).inverse(coeffs.contiguous())
+
+
+class Batched:
+    """Many streams of uneven geometry in one persistent launch (ct_plan_*).
+
+    streams: list of dicts with keys height, width, levels, dirs, planes
+    ([batch, H, W] float32 CUDA tensor) and steps ([nsub] or [batch, nsub]
+    float32 CUDA tensor). Output buffers are allocated here and exposed per
+    stream as coeffs, idx, side, deq, out.
+    """
+
+    def __init__(self, streams, graph=True, autotune=False, device="cuda"):
+        self.device = torch.device(device)
+        self.streams = []
+        descs = (StreamDesc * len(streams))()
+        for i, st in enumerate(streams):
+            H, W, J, dirs = st["height"], st["width"], st["levels"], st["dirs"]
+            planes = st["planes"]
+            B = planes.shape[0]
+            lay, _ = layout(H, W, J, dirs)
+            n = int(lay.ncoef)
+            steps = st["steps"].contiguous()
+            stride = 0 if steps.dim() == 1 else int(lay.nsub)
+            rec = dict(height=H, width=W, levels=J, dirs=list(dirs), batch=B, ncoef=n,
+                       planes=planes.contiguous(), steps=steps,
+                       coeffs=torch.empty((B, n), dtype=torch.float32, device=self.device),
+                       idx=torch.empty((B, n), dtype=torch.int16, device=self.device),
+                       side=torch.empty((B, 2), dtype=torch.float32, device=self.device),
+                       deq=torch.empty((B, n), dtype=torch.float32, device=self.device),
+                       out=torch.empty((B, H, W), dtype=torch.float32, device=self.device))
+            self.streams.append(rec)
+            d = descs[i]
+            d.geom = geom(H, W, J, dirs)
+            d.batch = B
+            d.planes = rec["planes"].data_ptr()
+            d.coeffs = rec["coeffs"].data_ptr()
+            d.idx = rec["idx"].data_ptr()
+            d.side = rec["side"].data_ptr()
+            d.steps = steps.data_ptr()
+            d.steps_stride = stride
+            d.deq = rec["deq"].data_ptr()
+            d.out = rec["out"].data_ptr()
+        flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0)
+        handle = ctypes.c_void_p()
+        torch.cuda.synchronize(self.device)
+        _check("ct_plan_create", _lib().ct_plan_create(descs, len(streams), flags, ctypes.byref(handle)))
+        self.handle = handle
+
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def run(self):
+        _check("ct_plan_run", _lib().ct_plan_run(self.handle, self._stream()))
+
+    def run_plain(self):
+        _check("ct_plan_run_plain", _lib().ct_plan_run_plain(self.handle, self._stream()))
+
+    def info(self):
+        inf = PlanInfo()
+        _check("ct_plan_info", _lib().ct_plan_info(self.handle, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in PlanInfo._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
+            _lib().ct_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

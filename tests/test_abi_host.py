@@ -114,3 +114,34 @@ def test_fault_injection_hook(ct, monkeypatch):
     assert lib.ct_forward(ctypes.byref(g), 1, dummy, dummy, dummy, need, None) == -4
     assert lib.ct_quantize(ctypes.byref(g), 1, dummy, dummy, 0, dummy, dummy, dummy, need, None) == -4
     assert lib.ct_strerror(-4) == b"HIP runtime error"
+
+
+def test_plan_validation_errors(ct):
+    lib = ct._lib()
+    handle = ctypes.c_void_p()
+    assert lib.ct_plan_create(None, 1, 0, ctypes.byref(handle)) == -1
+    descs = (ct.StreamDesc * 1)()
+    assert lib.ct_plan_create(descs, 0, 0, ctypes.byref(handle)) == -1
+    assert lib.ct_plan_create(descs, 1, 0, None) == -1
+    d = descs[0]
+    d.geom = ct.geom(256, 256, 2, [8, 4])
+    d.batch = 1
+    dummy = 0x1000
+    d.planes = d.coeffs = d.idx = d.side = d.steps = d.deq = d.out = dummy
+    d.steps_stride = 3                         # shorter than nsub
+    assert lib.ct_plan_create(descs, 1, 0, ctypes.byref(handle)) == -1
+    d.steps_stride = 0
+    d.out = None
+    assert lib.ct_plan_create(descs, 1, 0, ctypes.byref(handle)) == -1
+    d.out = dummy
+    d.geom = ct.geom(256, 256, 2, [8, 6])      # not a power of two
+    assert lib.ct_plan_create(descs, 1, 0, ctypes.byref(handle)) == -2
+    d.geom = ct.geom(256, 256, 2, [8, 4])
+    d.batch = 0
+    assert lib.ct_plan_create(descs, 1, 0, ctypes.byref(handle)) == -1
+    assert handle.value is None
+    assert lib.ct_plan_run(None, None) == -1
+    assert lib.ct_plan_run_plain(None, None) == -1
+    info = ct.PlanInfo()
+    assert lib.ct_plan_info(None, ctypes.byref(info)) == -1
+    lib.ct_plan_destroy(None)

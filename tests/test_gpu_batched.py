@@ -1,0 +1,142 @@
+"""GPU tests of the batched form (one persistent, graph-captured launch).
+
+Mixed streams of uneven resolution, LP depth and direction counts run
+forward + quantise + dequantise + inverse in one launch; the result must be
+bit-identical to the per-stream plain launches of the same plan, and agree
+with the oracle.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ct as oct
+from oracle import geometry as geo
+from oracle import quant as oq
+from paper_1510_00561_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+STREAMS = [
+    (240, 320, 2, [8, 8], 3),
+    (480, 640, 3, [16, 8, 8], 3),
+    (720, 1280, 4, [16, 8, 8, 8], 1),
+    (240, 320, 4, [8, 8, 8, 8], 3),
+    (70, 90, 3, [16, 8, 4], 2),
+    (64, 96, 2, [4, 32], 1),
+    (256, 256, 2, [8, 4], 1),
+]
+
+
+def _streams(seed=0):
+    from paper_1510_00561_amd import ct
+    rng = np.random.default_rng(seed)
+    out = []
+    for H, W, J, dirs, B in STREAMS:
+        planes = rng.uniform(0, 255, (B, H, W)).astype(np.float32)
+        nsub = int(ct.layout(H, W, J, dirs)[0].nsub)
+        steps = rng.integers(4, 65, size=(B, nsub)).astype(np.float32)
+        out.append(dict(height=H, width=W, levels=J, dirs=dirs,
+                        planes=torch.from_numpy(planes).cuda(), steps=torch.from_numpy(steps).cuda()))
+    return out
+
+
+def _snapshot(plan):
+    return [{k: s[k].clone() for k in ("coeffs", "idx", "side", "deq", "out")} for s in plan.streams]
+
+
+def _same(a, b):
+    for x, y in zip(a, b):
+        for k in x:
+            assert torch.equal(x[k], y[k]), k
+
+
+def test_batched_equals_plain_and_replays():
+    from paper_1510_00561_amd import ct
+    print("[batched] graph plan over", len(STREAMS), "streams", flush=True)
+    plan = ct.Batched(_streams(), graph=True)
+    info = plan.info()
+    assert info["graph"] == 1 and info["streams"] == len(STREAMS)
+    plan.run_plain()
+    torch.cuda.synchronize()
+    plain = _snapshot(plan)
+    for s in plan.streams:
+        for k in ("coeffs", "idx", "side", "deq", "out"):
+            s[k].zero_()
+    for rep in range(3):
+        plan.run()
+        torch.cuda.synchronize()
+        _same(plain, _snapshot(plan))
+        # eager work between replays, then wipe the outputs
+        torch.cuda.synchronize()
+        for s in plan.streams:
+            s["out"].fill_(-1.0)
+    plan.close()
+
+
+def test_batched_without_graph_matches():
+    from paper_1510_00561_amd import ct
+    plan = ct.Batched(_streams(1), graph=False)
+    plan.run()
+    torch.cuda.synchronize()
+    a = _snapshot(plan)
+    plan.run_plain()
+    torch.cuda.synchronize()
+    _same(a, _snapshot(plan))
+    plan.close()
+
+
+def test_batched_parity_with_oracle():
+    from paper_1510_00561_amd import ct
+    plan = ct.Batched(_streams(2), graph=True)
+    plan.run()
+    torch.cuda.synchronize()
+    for (H, W, J, dirs, B), s in zip(STREAMS, plan.streams):
+        if H * W > 500_000:
+            continue
+        print(f"[batched] oracle check {H}x{W} J={J} dirs={dirs}", flush=True)
+        table = geo.subband_table(H, W, J, dirs)
+        x = s["planes"].cpu().numpy()
+        coeffs = s["coeffs"].cpu().numpy()
+        idx = s["idx"].cpu().numpy()
+        deq = s["deq"].cpu().numpy()
+        out = s["out"].cpu().numpy()
+        steps = s["steps"].cpu().numpy()
+        for b in range(min(B, 2)):
+            ref = oct.forward(x[b].astype(np.float64), J, dirs)
+            assert np.abs(coeffs[b] - ref).max() <= 1e-3
+            q, side = oq.quantize32(coeffs[b], steps[b], table)
+            np.testing.assert_array_equal(idx[b], q)
+            np.testing.assert_array_equal(deq[b], oq.dequantize32(q, steps[b], side, table))
+            rec = oct.inverse(deq[b].astype(np.float64), H, W, J, dirs)
+            assert np.abs(out[b] - rec).max() <= 1e-3
+    plan.close()
+
+
+def test_autotuned_plan(tmp_path, monkeypatch):
+    from paper_1510_00561_amd import ct
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("CT_AUTOTUNE_CACHE", str(cache))
+    plan = ct.Batched(_streams(3), graph=True, autotune=True)
+    info = plan.info()
+    assert info["autotuned"] == 1
+    assert info["levels_paired"] + info["levels_single"] > 0
+    assert cache.exists()
+    entries = json.loads(cache.read_text())
+    assert entries and all(v in (1, 2) for v in entries.values())
+    plan.run()
+    torch.cuda.synchronize()
+    tuned = _snapshot(plan)
+    plan.close()
+    # a second plan reads the cache and gives the same answer as a default plan
+    ref = ct.Batched(_streams(3), graph=True)
+    ref.run()
+    torch.cuda.synchronize()
+    for x, y in zip(tuned, _snapshot(ref)):
+        assert torch.allclose(x["coeffs"], y["coeffs"], atol=1e-4)
+        # the two tile shapes round alike, so at most a few indices sit on
+        # the other side of a rounding boundary
+        assert (x["idx"] != y["idx"]).float().mean().item() < 1e-4
+    ref.close()
