@@ -29,16 +29,16 @@ PLANES = 3 * FRAMES
 
 # kernel -> sources whose text defines it (a change invalidates its counters)
 KERNEL_SOURCES = {
-    "lp_dfb12_analysis": ("ct_level.hip", "ct_stages.h", "ct_device.h"),
-    "dfb12_lp_synthesis": ("ct_level.hip", "ct_stages.h", "ct_device.h"),
-    "dfb_split_analysis": ("ct_level.hip", "ct_stages.h", "ct_device.h"),
-    "dfb_split_synthesis": ("ct_level.hip", "ct_stages.h", "ct_device.h"),
-    "dfb_split2_analysis": ("ct_level.hip", "ct_stages.h", "ct_device.h"),
-    "dfb_split2_synthesis": ("ct_level.hip", "ct_stages.h", "ct_device.h"),
+    "lp_dfb12_analysis": ("ct_level.hip", "ct_stream_level.h", "ct_stream.h", "ct_kernels.h"),
+    "dfb12_lp_synthesis": ("ct_level.hip", "ct_stream_level.h", "ct_stream.h", "ct_kernels.h"),
+    "dfb_split_analysis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h"),
+    "dfb_split_synthesis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h"),
+    "dfb_split2_analysis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h"),
+    "dfb_split2_synthesis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h"),
     "pad_fold": ("ct_level.hip",),
-    "lowpass_partial": ("ct_quant.hip",),
-    "quantize": ("ct_quant.hip",),
-    "dequantize": ("ct_quant.hip",),
+    "lowpass_partial": ("ct_quant.hip", "ct_quant_stages.h"),
+    "quantize": ("ct_quant.hip", "ct_quant_stages.h"),
+    "dequantize": ("ct_quant.hip", "ct_quant_stages.h"),
 }
 
 
@@ -95,8 +95,8 @@ def cpu_baseline(planes_np, steps_np, seconds_budget=30.0):
 
 def batched_comparison(steps):
     """Mixed workload: 64 streams (one YCoCg frame each) of 320x240, 640x480 or
-    1280x720, LP depth 2-4, 8-16 directions, in one persistent graph launch
-    vs the same work as per-stream plain launches."""
+    1280x720, LP depth 2-4, 8-16 directions, as one graph launch of grouped
+    kernels vs the same work as per-stream, per-stage plain launches."""
     import numpy as np
     import torch
     from paper_1510_00561_amd import ct, synth
@@ -110,8 +110,8 @@ def batched_comparison(steps):
         fr = i % 8
         planes = torch.from_numpy(np.ascontiguousarray(clips[(h, w)][3 * fr:3 * fr + 3])).cuda()
         nsub = int(ct.layout(h, w, J, dirs)[0].nsub)
-        steps = torch.from_numpy(rng.integers(4, 65, size=(3, nsub)).astype(np.float32)).cuda()
-        descs.append(dict(height=h, width=w, levels=J, dirs=dirs, planes=planes, steps=steps))
+        step_table = torch.from_numpy(rng.integers(4, 65, size=(3, nsub)).astype(np.float32)).cuda()
+        descs.append(dict(height=h, width=w, levels=J, dirs=dirs, planes=planes, steps=step_table))
     plan = ct.Batched(descs, graph=True, autotune=True)
     plan.run()
     plan.run_plain()

@@ -181,8 +181,8 @@ int ct_inverse_adjoint(const ct_geom* geom, int32_t batch, const float* gplanes,
 
 /*
  * Batched form: many streams of uneven resolution and LP depth run one pass
- * of the hot path (forward CT, quantise, dequantise, inverse CT) in ONE
- * persistent launch. Each stream is `batch` planes of one geometry with its
+ * of the hot path (forward CT, quantise, dequantise, inverse CT) in one graph
+ * launch. Each stream is `batch` planes of one geometry with its
  * own caller-owned device buffers:
  *   planes  [batch][H][W] float32 input
  *   coeffs  [batch][ncoef] float32 forward output
@@ -191,14 +191,16 @@ int ct_inverse_adjoint(const ct_geom* geom, int32_t batch, const float* gplanes,
  *   steps   step table as for ct_quantize (steps_stride 0: one shared row)
  *   deq     [batch][ncoef] float32 dequantised coefficients
  *   out     [batch][H][W] float32 reconstruction
- * ct_plan_create validates every stream, allocates the plan's own workspace,
- * stage tables and counters (the only device allocations of this library),
- * and with CT_PLAN_GRAPH captures [counter reset kernel, persistent kernel]
- * into a HIP graph. With CT_PLAN_AUTOTUNE it times the tile-shape choices of
- * the deeper DFB levels per level shape (pairs of tree levels on 64 x 64
- * sheared tiles, or single levels on 32 x 64 tiles) and caches them in a JSON
- * file (CT_AUTOTUNE_CACHE, default $HOME/.cache/ct_autotune.json).
- * ct_plan_run enqueues one graph launch (or the two kernels) on `stream`.
+ * ct_plan_create validates every stream, allocates the plan's own workspace
+ * and stage tables (the only device allocations of this library), and lays
+ * the work out in groups: the stages of one type at one chain position of
+ * all streams, run by one launch that covers all their tiles. The groups
+ * follow in chain order on one stream. With CT_PLAN_GRAPH the group launches
+ * are captured into one HIP graph. With CT_PLAN_AUTOTUNE it times, per LP
+ * level shape, whether the deeper DFB tree levels stream two at a time or
+ * one at a time and caches the choice in a JSON file (CT_AUTOTUNE_CACHE,
+ * default $HOME/.cache/ct_autotune.json).
+ * ct_plan_run enqueues one graph launch (or the group launches) on `stream`.
  * ct_plan_run_plain enqueues the same work as separate per-stream,
  * per-stage launches (the unbatched baseline); both give identical results.
  * A plan may not run on two streams at once; buffers are read and written
@@ -220,7 +222,7 @@ typedef struct ct_stream_desc {
 typedef struct ct_plan ct_plan;
 
 typedef struct ct_plan_info_t {
-    int32_t streams, stages, work_items, workgroups;
+    int32_t streams, stages, work_items, launches;
     int32_t graph, autotuned;
     int32_t levels_paired, levels_single;   /* tile-shape choices of levels with l >= 4 */
     int64_t workspace_bytes;

@@ -21,9 +21,9 @@ SOURCES = [
     ("ct_filters.cpp", []),
     ("ct_api.cpp", []),
     ("ct_plan.cpp", []),
-    ("ct_level.hip", []),
+    ("ct_level.hip", ["-ffp-contract=off"]),
     ("ct_quant.hip", ["-ffp-contract=off"]),
-    ("ct_batched.hip", []),
+    ("ct_batched.hip", ["-ffp-contract=off"]),
 ]
 
 COMMON = [

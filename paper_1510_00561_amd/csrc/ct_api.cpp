@@ -172,7 +172,6 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
     float* A = reinterpret_cast<float*>(ws + w.a_off);
     float* Bf = reinterpret_cast<float*>(ws + w.b_off);
     auto push = [&](StageDesc d) {
-        d.dep = -1;                        // chains are linked by their user
         d.batch = batch;
         d.lift = L;
         d.lo_r = lo_r;
@@ -216,7 +215,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
             a.up = up;
             a.L = L;
             a.batch = batch;
-            d.ntiles = ((Cj + 63) / 64) * ((Rj + 63) / 64) * batch;
+            d.ntiles = level_stage_tiles(Rj, Cj, batch);
             d.bytes = 4.0 * batch * (double(a.src_h) * a.src_w + double(Rj / 2) * (Cj / 2) + double(Rj) * Cj);
             push(d);
             int first[4], count[4];
@@ -330,7 +329,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
         a.up = up;
         a.L = L;
         a.batch = batch;
-        d.ntiles = ((Cj + 63) / 64) * ((Rj + 63) / 64) * batch;
+        d.ntiles = level_stage_tiles(Rj, Cj, batch);
         d.bytes = 4.0 * batch * (double(Rj / 2) * (Cj / 2) + double(Rj) * Cj + double(a.out_h) * a.out_w);
         push(d);
     }
@@ -433,6 +432,8 @@ int transform(const ct_geom* geom, int32_t batch, const float* in, float* out, v
 
 namespace ct {
 
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 int fill_quant_args(const Geometry& g, QuantArgs* a) {
     if (g.nsub + 1 > int(sizeof(a->sub_off) / sizeof(a->sub_off[0]))) return CT_ERR_GEOM;
     std::vector<ct_subband> table(g.nsub);
@@ -464,8 +465,8 @@ int build_quant_chain(const Geometry& g, int batch, const float* coeffs, const f
     a.steps = steps;
     a.steps_stride = steps_stride;
     a.partials = reinterpret_cast<float*>(ws + w.part_off);
+    a.vec8 = g.ncoef % 8 == 0 && aligned16(coeffs) && aligned16(idx);
     d.batch = batch;
-    d.dep = -1;
     d.type = kStPartial;
     d.ntiles = a.nparts * batch;
     d.bytes = 4.0 * batch * double(g.low_n);
@@ -487,11 +488,11 @@ int build_dequant_chain(const Geometry& g, int batch, const int16_t* idx, const 
     QuantArgs& a = d.u.q;
     a.idx_in = idx;
     a.coeffs_out = coeffs;
+    a.vec8 = g.ncoef % 8 == 0 && aligned16(idx) && aligned16(coeffs);
     a.side = const_cast<float*>(side);
     a.steps = steps;
     a.steps_stride = steps_stride;
     d.batch = batch;
-    d.dep = -1;
     d.type = kStDequantize;
     d.ntiles = int((g.ncoef + 4095) / 4096) * batch;
     d.bytes = 6.0 * batch * double(g.ncoef);

@@ -1,12 +1,14 @@
 // Batched form: stage descriptors shared by the plan builder (host) and the
-// persistent work-queue kernel (device).
+// group kernels (device).
 //
 // A plan holds, for every stream, the chain of stages of one pass of the hot
 // path (forward CT, quantise, dequantise, inverse CT). Each stage is a set of
-// independent tiles; a stage may start once its predecessor in the chain has
-// finished all its tiles. Work items (stage, tile) are ordered wave by wave:
-// the first stage of every stream, then the second, ..., each wave largest
-// stream first, so a stage's predecessor is always earlier in the order.
+// independent tiles and may start once its predecessor in the chain has
+// finished. The plan runs the chains position by position: the stages at
+// one chain position of all streams are independent of each other, so those
+// of one type are laid end to end and run as one launch (a group), and the
+// launches follow in chain order on one stream, so that stream order carries
+// every dependency.
 #pragma once
 
 #include "ct_stages.h"
@@ -23,12 +25,12 @@ enum StageType : int {
     kStSplit1Syn = 6,
     kStSplit2Syn = 7,
     kStLevelSyn = 8,     // DFB tree levels 1-2 + LP level, synthesis
+    kStNumTypes = 9,
 };
 
 struct StageDesc {
     int type;
     int ntiles;
-    int dep;             // stage index of the predecessor, or -1
     int batch;
     int lo_r;            // reach of the LP `lo` filter: 4 (hbar) or 3 (gbar, transposes)
     double bytes;        // compulsory bytes (profiling)
@@ -41,13 +43,13 @@ struct StageDesc {
     } u;
 };
 
-constexpr int kBatchedThreads = 512;
+constexpr int kBatchedThreads = 256;
 
-// Launches the counter reset and the persistent kernel for `nstages` stages
-// with `total_items` work items. `counters` holds nstages + 1 ints.
-hipError_t launch_batched(const StageDesc* stages, const int* first_item, int nstages,
-                          int total_items, int* counters, int grid, hipStream_t s);
-// Workgroups of the persistent kernel that can be resident at once.
-int batched_capacity();
+// Launches one group: `n` stages of type `type` whose tiles are laid end to
+// end (stage i owns tiles [first[i], first[i+1]), `tiles` in total), one
+// workgroup of kBatchedThreads per tile. `stages` and `first` are device
+// arrays.
+hipError_t launch_group(int type, const StageDesc* stages, const int* first, int n, int tiles,
+                        hipStream_t s);
 
 }  // namespace ct

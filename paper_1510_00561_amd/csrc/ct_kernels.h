@@ -69,6 +69,46 @@ struct SplitArgs {
     float scale[64];    // per child channel (applied on store / load)
     int use_scale;
 };
+
+// Work decomposition of the register-streaming split stages (one or two tree
+// levels per pass): every wavefront stores a strip of stream_cols() sheared
+// columns by stream_rows() rows of one parent channel, and loads a halo of
+// stream_halo() rows and columns around it.
+__host__ __device__ constexpr int stream_halo(int levels) { return levels == 1 ? 4 : 12; }
+__host__ __device__ constexpr int stream_cols(int levels) { return 128 - 2 * stream_halo(levels); }
+__host__ __device__ constexpr int stream_rows(int levels) { return levels == 1 ? 248 : 216; }
+
+// Per plane: horizontal parents first (each with `ih` items, `sh` strips
+// across), then vertical ones (`iv`, `sv`).
+struct StreamCounts {
+    int nh, ih, iv, sh, sv;
+};
+__host__ __device__ inline StreamCounts stream_counts(const SplitArgs& a, int levels) {
+    const int t = a.t, vw = stream_cols(levels), bh = stream_rows(levels);
+    const int nrh = a.Rj >> (t - 2), nch = a.Cj >> 1;
+    const int nrv = a.Cj >> (t - 2), ncv = a.Rj >> 1;
+    StreamCounts c;
+    c.nh = 1 << (t - 2);
+    c.sh = (nch + vw - 1) / vw;
+    c.sv = (ncv + vw - 1) / vw;
+    c.ih = c.sh * ((nrh + bh - 1) / bh);
+    c.iv = c.sv * ((nrv + bh - 1) / bh);
+    return c;
+}
+__host__ __device__ inline int stream_items(const SplitArgs& a, int batch, int levels) {
+    const StreamCounts c = stream_counts(a, levels);
+    return c.nh * (c.ih + c.iv) * batch;
+}
+
+// Work decomposition of the register-streaming LP-level stages: every
+// wavefront stores a strip of level_cols() image columns by level_rows()
+// rows of one plane.
+__host__ __device__ constexpr int level_cols() { return 96; }
+__host__ __device__ constexpr int level_rows() { return 256; }
+__host__ __device__ inline int level_items(int R, int C, int batch) {
+    return ((C + level_cols() - 1) / level_cols()) * ((R + level_rows() - 1) / level_rows()) * batch;
+}
+
 hipError_t launch_dfb_split_analysis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
 hipError_t launch_dfb_split_synthesis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
 
@@ -109,6 +149,7 @@ struct QuantArgs {
     int64_t low_n;
     int nsub;
     int nparts;              // partial blocks per plane for the lowpass
+    int vec8;                // ncoef % 8 == 0 and 16-byte aligned arrays: 8-wide accesses
     int sub_off[386];        // subband start offsets + end sentinel
 };
 // Pass 1 (per-block lowpass min/max partials) and pass 2 (indices).

@@ -1,11 +1,11 @@
-// Batched plans: many streams of uneven resolution and LP depth in one
-// persistent launch (host side).
+// Batched plans: many streams of uneven resolution and LP depth in one graph
+// launch (host side).
 //
 // A plan owns a workspace slice per stream, the stage-descriptor table of
-// every stream's chain (forward CT, quantise, dequantise, inverse CT), the
-// work-item order, the completion counters and, with CT_PLAN_GRAPH, an
-// instantiated HIP graph of [counter reset, persistent kernel]. The counters
-// are cleared by a fill kernel inside the graph, never by a memset node.
+// every stream's chain (forward CT, quantise, dequantise, inverse CT) laid
+// out group by group, and, with CT_PLAN_GRAPH, an instantiated HIP graph of
+// the group launches. A group is the set of stages of one type at one chain
+// position over all streams; its launch covers all their tiles.
 //
 // Autotuning (CT_PLAN_AUTOTUNE) picks, for every distinct LP level shape
 // with four or more DFB tree levels, whether the deeper tree levels run in
@@ -39,12 +39,14 @@ struct ct_plan {
     char* ws = nullptr;
     std::vector<std::vector<StageDesc>> chains;     // per stream, chain order
     std::vector<int> grouping;                      // [stream * kMaxLevels + j]
+    struct Group {
+        int type, stage0, n, tiles;    // stages [stage0, stage0 + n) of d_stages / d_first
+    };
+    std::vector<Group> groups;
     StageDesc* d_stages = nullptr;
     int* d_first = nullptr;
-    int* d_counters = nullptr;
     int nstages = 0;
     int total_items = 0;
-    int grid = 0;
     double bytes = 0;
     hipStream_t capture = nullptr;
     hipGraph_t graph = nullptr;
@@ -219,6 +221,16 @@ int autotune(ct_plan* p, hipStream_t st) {
     return rc;
 }
 
+// The group launches of a plan, in chain order.
+hipError_t launch_groups(const ct_plan* p, hipStream_t st) {
+    for (const ct_plan::Group& g : p->groups) {
+        const hipError_t e = launch_group(g.type, p->d_stages + g.stage0, p->d_first + g.stage0, g.n,
+                                          g.tiles, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 void free_plan(ct_plan* p) {
     if (!p) return;
     if (p->exec) hipGraphExecDestroy(p->exec);
@@ -226,7 +238,6 @@ void free_plan(ct_plan* p) {
     if (p->capture) hipStreamDestroy(p->capture);
     if (p->d_stages) hipFree(p->d_stages);
     if (p->d_first) hipFree(p->d_first);
-    if (p->d_counters) hipFree(p->d_counters);
     if (p->ws) hipFree(p->ws);
     delete p;
 }
@@ -303,45 +314,40 @@ int ct_plan_create(const ct_stream_desc* streams, int32_t n, int32_t flags, ct_p
         build_transform_chain(g, d.batch, kModeInverse, d.deq, d.out, ws, p->wls[s], grp, c);
         max_len = std::max(max_len, c.size());
     }
-    // work order: wave by wave (chain position), largest stage first
+    // groups: chain position by chain position, one group per stage type,
+    // each group's stages largest first
     std::vector<StageDesc> order;
-    std::vector<int> prev(n, -1);
+    std::vector<int> first;
+    int64_t items = 0;
     for (size_t w = 0; w < max_len; ++w) {
-        std::vector<int> ids;
-        for (int s = 0; s < n; ++s)
-            if (p->chains[s].size() > w) ids.push_back(s);
-        std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
-            return p->chains[a][w].ntiles > p->chains[b][w].ntiles;
-        });
-        for (int s : ids) {
-            StageDesc d = p->chains[s][w];
-            d.dep = prev[s];
-            prev[s] = int(order.size());
-            p->bytes += d.bytes;
-            order.push_back(d);
+        for (int type = 0; type < kStNumTypes; ++type) {
+            std::vector<int> ids;
+            for (int s = 0; s < n; ++s)
+                if (p->chains[s].size() > w && p->chains[s][w].type == type) ids.push_back(s);
+            if (ids.empty()) continue;
+            std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) {
+                return p->chains[a][w].ntiles > p->chains[b][w].ntiles;
+            });
+            ct_plan::Group g{type, int(order.size()), int(ids.size()), 0};
+            for (int s : ids) {
+                const StageDesc& d = p->chains[s][w];
+                first.push_back(g.tiles);
+                g.tiles += d.ntiles;
+                p->bytes += d.bytes;
+                order.push_back(d);
+            }
+            items += g.tiles;
+            p->groups.push_back(g);
         }
     }
     p->nstages = int(order.size());
-    std::vector<int> first(order.size());
-    int64_t items = 0;
-    for (size_t i = 0; i < order.size(); ++i) {
-        first[i] = int(items);
-        items += order[i].ntiles;
-    }
     if (items >= (int64_t(1) << 31)) {
         free_plan(p);
         return CT_ERR_UNSUPPORTED;
     }
     p->total_items = int(items);
-    const int cap = batched_capacity();
-    if (cap <= 0) {
-        free_plan(p);
-        return CT_ERR_HIP;
-    }
-    p->grid = std::min(cap, p->total_items);
     if (hipMalloc(&p->d_stages, sizeof(StageDesc) * order.size()) != hipSuccess ||
         hipMalloc(&p->d_first, sizeof(int) * first.size()) != hipSuccess ||
-        hipMalloc(&p->d_counters, sizeof(int) * (order.size() + 1)) != hipSuccess ||
         hipMemcpy(p->d_stages, order.data(), sizeof(StageDesc) * order.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_first, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice) != hipSuccess) {
         free_plan(p);
@@ -349,9 +355,7 @@ int ct_plan_create(const ct_stream_desc* streams, int32_t n, int32_t flags, ct_p
     }
     if (flags & CT_PLAN_GRAPH) {
         bool ok = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        if (ok)
-            ok = launch_batched(p->d_stages, p->d_first, p->nstages, p->total_items, p->d_counters,
-                                p->grid, p->capture) == hipSuccess;
+        if (ok) ok = launch_groups(p, p->capture) == hipSuccess;
         hipGraph_t graph = nullptr;
         const bool ended = hipStreamEndCapture(p->capture, &graph) == hipSuccess;
         p->graph = graph;
@@ -371,10 +375,7 @@ int ct_plan_run(ct_plan* p, hipStream_t stream) {
         CT_PROFILED("batched_graph", p->bytes, hipGraphLaunch(p->exec, stream), stream);
         return CT_OK;
     }
-    CT_PROFILED("batched", p->bytes,
-                launch_batched(p->d_stages, p->d_first, p->nstages, p->total_items, p->d_counters,
-                               p->grid, stream),
-                stream);
+    CT_PROFILED("batched", p->bytes, launch_groups(p, stream), stream);
     return CT_OK;
 }
 
@@ -392,7 +393,7 @@ int ct_plan_info(const ct_plan* p, ct_plan_info_t* info) {
     info->streams = int32_t(p->streams.size());
     info->stages = p->nstages;
     info->work_items = p->total_items;
-    info->workgroups = p->grid;
+    info->launches = int32_t(p->groups.size());
     info->graph = p->exec ? 1 : 0;
     info->autotuned = p->autotuned;
     int pairs = 0, singles = 0;

@@ -43,13 +43,18 @@ int launch_stage(const StageDesc& d, hipStream_t st);
 int launch_chain(const std::vector<StageDesc>& chain, hipStream_t st);
 int fill_quant_args(const Geometry& g, QuantArgs* a);
 
-// Tiles of a DFB split stage covering `levels` (1 or 2) tree levels.
+// Work-queue tiles of an LP-level stage (one wavefront item per strip and
+// row block, kBatchedThreads / 64 per tile).
+inline int level_stage_tiles(int R, int C, int batch) {
+    constexpr int waves = kBatchedThreads / 64;
+    return (level_items(R, C, batch) + waves - 1) / waves;
+}
+
+// Work-queue tiles of a DFB split stage covering `levels` (1 or 2) tree
+// levels: one wavefront item per strip, kBatchedThreads / 64 per tile.
 inline int split_stage_tiles(const SplitArgs& a, int batch, int levels) {
-    const int tr = levels == 1 ? 32 : 64, tc = 64;
-    const int t = a.t;
-    const int th = (((a.Rj >> (t - 2)) + tr - 1) / tr) * (((a.Cj >> 1) + tc - 1) / tc);
-    const int tv = (((a.Cj >> (t - 2)) + tr - 1) / tr) * (((a.Rj >> 1) + tc - 1) / tc);
-    return (1 << (t - 2)) * (th + tv) * batch;
+    constexpr int waves = kBatchedThreads / 64;
+    return (stream_items(a, batch, levels) + waves - 1) / waves;
 }
 
 }  // namespace ct

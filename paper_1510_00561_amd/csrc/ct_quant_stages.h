@@ -111,6 +111,45 @@ __device__ void quantize(const QuantArgs& A, int tile, float* red) {
     const float* c = A.coeffs + b * A.ncoef;
     int16_t* q = A.idx + b * A.ncoef;
     const float* steps = A.steps + int64_t(b) * A.steps_stride;
+    const int64_t e_end = e0 + CHUNK < A.ncoef ? e0 + CHUNK : A.ncoef;
+    const int s0 = find_subband(A, e0);
+    if (A.vec8 && A.sub_off[s0 + 1] >= e_end) {
+        // the whole chunk lies in one subband: 8 consecutive coefficients per
+        // thread, 32-byte loads and a 16-byte store
+        constexpr int IT = (CHUNK / 8 + NT - 1) / NT;
+        const float step = steps[s0];
+        float4 xa[IT], xb[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int64_t e = e0 + 8 * (threadIdx.x + it * NT);
+            if (e < e_end) {
+                xa[it] = *reinterpret_cast<const float4*>(c + e);
+                xb[it] = *reinterpret_cast<const float4*>(c + e + 4);
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int64_t e = e0 + 8 * (threadIdx.x + it * NT);
+            if (e >= e_end) break;
+            const float x[8] = {xa[it].x, xa[it].y, xa[it].z, xa[it].w,
+                                xb[it].x, xb[it].y, xb[it].z, xb[it].w};
+            uint32_t w[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                uint32_t pair[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const float xv = x[2 * h + u];
+                    const float v = s0 == 0 ? __fdiv_rn(__fmul_rn(__fsub_rn(xv, mn), sc), step)
+                                            : __fdiv_rn(xv, step);
+                    pair[u] = uint32_t(uint16_t(to_index(v)));
+                }
+                w[h] = pair[0] | (pair[1] << 16);
+            }
+            *reinterpret_cast<uint4*>(q + e) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        return;
+    }
     const int64_t e_first = e0 + threadIdx.x;
     if (e_first >= A.ncoef) return;
     float xs[ITEMS];
@@ -153,6 +192,35 @@ __device__ void dequantize(const QuantArgs& A, int tile) {
     const int16_t* q = A.idx_in + b * A.ncoef;
     float* out = A.coeffs_out + b * A.ncoef;
     const float* steps = A.steps + int64_t(b) * A.steps_stride;
+    const int64_t e_end = e0 + CHUNK < A.ncoef ? e0 + CHUNK : A.ncoef;
+    const int s0 = find_subband(A, e0);
+    if (A.vec8 && A.sub_off[s0 + 1] >= e_end) {
+        // one subband: a 16-byte load and two 16-byte stores per thread
+        constexpr int IT = (CHUNK / 8 + NT - 1) / NT;
+        const float step = steps[s0];
+        uint4 qa[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int64_t e = e0 + 8 * (threadIdx.x + it * NT);
+            if (e < e_end) qa[it] = *reinterpret_cast<const uint4*>(q + e);
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int64_t e = e0 + 8 * (threadIdx.x + it * NT);
+            if (e >= e_end) break;
+            const uint32_t w[4] = {qa[it].x, qa[it].y, qa[it].z, qa[it].w};
+            float y[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int16_t qi = int16_t(uint16_t(w[u >> 1] >> (16 * (u & 1))));
+                const float v = __fmul_rn((float)qi, step);
+                y[u] = s0 == 0 ? __fadd_rn(mn, __fmul_rn(v, r)) : v;
+            }
+            *reinterpret_cast<float4*>(out + e) = make_float4(y[0], y[1], y[2], y[3]);
+            *reinterpret_cast<float4*>(out + e + 4) = make_float4(y[4], y[5], y[6], y[7]);
+        }
+        return;
+    }
     const int64_t e_first = e0 + threadIdx.x;
     if (e_first >= A.ncoef) return;
     int16_t qs[ITEMS];

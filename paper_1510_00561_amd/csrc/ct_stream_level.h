@@ -1,0 +1,528 @@
+// Register-streaming form of one LP level fused with DFB tree levels 1 and 2
+// (analysis), for gfx950.
+//
+// Paper section 2.1 (Laplacian pyramid, then the DFB on the bandpass image,
+// 9-7 filters), section 3.3 (the lowpass at half resolution per level).
+//
+// A wavefront owns a strip of 128 image columns (lane l holds columns
+// 2l and 2l + 1, i.e. lowpass column l) and streams down a block of rows.
+// Per pair of image rows (a superstep):
+//   hf  = horizontal lowpass of each new row            (lanes via DPP)
+//   c   = vertical lowpass of hf, one lowpass row         (register ring)
+//   uh  = horizontal upsampling of that lowpass row       (DPP)
+//   d   = x - vertical upsampling of uh, two bandpass rows
+//   DFB tree level 1 (4 lifting steps), level 2 (4 steps), each one row
+//       further behind than the previous, on the d rows
+// and the two rows leaving the last step are the four quarter channels of
+// tree level 2. Horizontal-cone channels are stored row by row; the
+// vertical-cone ones are stored transposed, so they are gathered in a
+// wave-private LDS block of 16 compact rows and written out column-wise.
+//
+// Lags (rows behind the newest loaded row 2n + 1, relative to the first
+// streamed row): c row n - 2, d rows 2n - 8 and 2n - 7, final rows 2n - 16
+// and 2n - 15. An output row depends on input rows from 17 above to 16
+// below it; blocks load 18 rows above and 16 below, and 16 columns on each
+// side of the 96 columns they store.
+#pragma once
+
+#include "ct_stream.h"
+
+namespace ct {
+namespace stream {
+
+// Horizontal lowpass at lowpass column l (image column 2l):
+// sum_k lo[k] x[2l +- k].
+template <int LO_R>
+__device__ __forceinline__ float row_lowpass(const Taps5& lo, float x0, float x1) {
+    const float p1 = from_prev(x1);                         // x[2l - 1]
+    const float n0 = from_next(x0), p0 = from_prev(x0);     // x[2l + 2], x[2l - 2]
+    float acc = lo.t[0] * x0;
+    acc = fmaf(lo.t[1], p1 + x1, acc);
+    acc = fmaf(lo.t[2], p0 + n0, acc);
+    if (LO_R >= 3) acc = fmaf(lo.t[3], from_prev(p1) + from_next(x1), acc);   // x[2l - 3], x[2l + 3]
+    if (LO_R >= 4) acc = fmaf(lo.t[4], from_prev(p0) + from_next(n0), acc);   // x[2l - 4], x[2l + 4]
+    return acc;
+}
+
+// Vertical lowpass from 2 LO_R + 1 rows h[0..2 LO_R] centred on h[LO_R].
+template <int LO_R>
+__device__ __forceinline__ float col_lowpass(const Taps5& lo, const float* h) {
+    float acc = lo.t[0] * h[LO_R];
+#pragma unroll
+    for (int k = 1; k <= LO_R; ++k) acc = fmaf(lo.t[k], h[LO_R - k] + h[LO_R + k], acc);
+    return acc;
+}
+
+// Horizontal upsampling of a lowpass row (value c at lowpass column l, i.e.
+// image column 2l): outputs at image columns 2l (.x) and 2l + 1 (.y).
+template <int UP_R>
+__device__ __forceinline__ Pair row_upsample(const Taps5& up, float c) {
+    const float cn = from_next(c), cp = from_prev(c);   // c[l + 1], c[l - 1]
+    Pair r;
+    float e = up.t[0] * c;
+    e = fmaf(up.t[2], cp + cn, e);
+    float o = up.t[1] * (c + cn);
+    if (UP_R >= 3) o = fmaf(up.t[3], cp + from_next(cn), o);   // c[l - 1], c[l + 2]
+    if (UP_R >= 4) e = fmaf(up.t[4], from_prev(cp) + from_next(cn), e);
+    r.x = e;
+    r.y = o;
+    return r;
+}
+
+template <int LO_R, int UP_R, int NT>
+struct StreamLevelAna {
+    static constexpr int WAVES = NT / 64;
+    static constexpr int HC = 16;            // halo image columns on each side
+    static constexpr int VW = level_cols();  // stored image columns per strip (128 - 2 HC)
+    static constexpr int TOP = 18;           // rows loaded above a block
+    static constexpr int LAG = 16;           // rows from the newest loaded row to the output
+    static constexpr int BH = level_rows();  // stored image rows per block
+    static constexpr int U = 6;              // supersteps per ring cycle
+    static constexpr int RR = 12;            // ring rows: x, hf and d
+    static constexpr int RC = 6;             // ring rows: uh (lowpass rows)
+    static constexpr int VB = 16;            // compact rows per transposed flush
+    static constexpr int VLD = VB + 1;
+    static constexpr int WAVE_SMEM = 2 * 64 * VLD;
+    static constexpr int SMEM = WAVES * WAVE_SMEM;   // floats
+
+    const stage::LevelAnaArgs& A;
+    __device__ StreamLevelAna(const stage::LevelAnaArgs& a) : A(a) {}
+
+    static_assert(VW == 128 - 2 * HC, "strip geometry");
+    __device__ int strips() const { return (A.C + VW - 1) / VW; }
+    __device__ int blocks() const { return (A.R + BH - 1) / BH; }
+    __device__ int items() const { return level_items(A.R, A.C, A.batch); }
+    __device__ int tiles() const { return (items() + WAVES - 1) / WAVES; }
+
+    static constexpr int rslot(int rel) { return ((rel % RR) + RR) % RR; }
+    static constexpr int cslot(int rel) { return ((rel % RC) + RC) % RC; }
+
+    __device__ void run_tile(int tile, float* smem) const {
+        const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+        const int item = tile * WAVES + wave;
+        if (item < items()) {
+            float* T = smem + wave * WAVE_SMEM;
+            if (A.L.first_odd) run<1>(item, T);
+            else run<0>(item, T);
+        }
+    }
+
+    template <int FO>
+    __device__ void run(int item, float* T) const {
+        const int ns = strips(), nb = blocks();
+        const int b = item / (ns * nb);
+        const int rem = item - b * ns * nb;
+        const int blk = rem / ns, strip = rem - blk * ns;
+        const int R = A.R, C = A.C, Rh = R >> 1, Ch = C >> 1;
+        const int kb = strip * VW, rb = blk * BH;
+        const int re = min(rb + BH, R);
+        const int lane = threadIdx.x & 63;
+        const int cb0 = kb - HC;                    // image column of lane 0's x0 (even)
+        const int kc = (cb0 >> 1) + lane;           // this lane's compact column (unwrapped)
+        const bool own = lane >= HC / 2 && lane < 64 - HC / 2 && kc < Ch;
+        const int S = rb - TOP;                     // first streamed row (even)
+        const int NS = (re - rb) / 2 + (TOP - 1);   // supersteps until the last output row
+
+        // source columns of the lane's two image columns (periodic, then
+        // padded past the real frame); zero padding clears the loaded bits
+        // with a mask, so every load is unconditional
+        const float* sp = A.src.p + b * A.src.plane;
+        int sc[2];
+        uint32_t mc[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            int g = pmod(cb0 + 2 * lane + e, C);
+            mc[e] = ~0u;
+            if (A.pad_mode == kPadReflect && g >= A.src_w) g = 2 * A.src_w - 1 - g;
+            if (A.pad_mode == kPadZero && g >= A.src_w) {
+                mc[e] = 0u;
+                g = 0;
+            }
+            sc[e] = g;
+        }
+        int xrow = pmod(S, R);                      // next row to load, modulo R
+        auto load_row = [&](Pair& X) {
+            int g = xrow;
+            uint32_t mr = ~0u;
+            if (A.pad_mode == kPadReflect && g >= A.src_h) g = 2 * A.src_h - 1 - g;
+            if (A.pad_mode == kPadZero && g >= A.src_h) {
+                mr = 0u;
+                g = 0;
+            }
+            const float* rp = sp + int64_t(g) * A.src.ld;
+            X.x = __uint_as_float(__float_as_uint(rp[sc[0]]) & (mr & mc[0]));
+            X.y = __uint_as_float(__float_as_uint(rp[sc[1]]) & (mr & mc[1]));
+            xrow = xrow + 1 == R ? 0 : xrow + 1;
+        };
+
+        float* cp = A.c_out.p + b * A.c_out.plane;
+        float* q0 = A.out.p[0] + b * A.out.plane;
+        float* q1 = A.out.p[1] + b * A.out.plane;
+        float* q2 = A.out.p[2] + b * A.out.plane;
+        float* q3 = A.out.p[3] + b * A.out.plane;
+        const float s0 = A.out.scale[0], s1 = A.out.scale[1];
+        const float s2 = A.out.scale[2], s3 = A.out.scale[3];
+
+        // transposed flush of `cnt` compact rows starting at compact row i0:
+        // four compact columns per instruction, VB rows each
+        auto flush = [&](int i0, int cnt) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int li = lane & (VB - 1), lk = lane >> 4;
+#pragma unroll
+            for (int kk = HC / 2; kk < 64 - HC / 2; kk += 4) {
+                const int l = kk + lk;
+                const int k = (cb0 >> 1) + l;
+                if (li < cnt && k < Ch) {
+                    const int64_t o = int64_t(k) * Rh + i0 + li;
+                    q2[o] = T[l * VLD + li];
+                    q3[o] = T[(64 + l) * VLD + li];
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+
+        Pair xr[RR], dr[RR];
+        float hf[RR];
+        Pair uh[RC];
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+            xr[r] = Pair{0.f, 0.f};
+            dr[r] = Pair{0.f, 0.f};
+            hf[r] = 0.f;
+        }
+#pragma unroll
+        for (int r = 0; r < RC; ++r) uh[r] = Pair{0.f, 0.f};
+
+        load_row(xr[0]);
+        load_row(xr[1]);
+        for (int n0 = 0; n0 < NS; n0 += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int n = n0 + u;
+                // prefetch the next pair of rows
+                load_row(xr[rslot(2 * u + 2)]);
+                load_row(xr[rslot(2 * u + 3)]);
+                // horizontal lowpass of rows 2n, 2n + 1
+                hf[rslot(2 * u)] = row_lowpass<LO_R>(A.lo, xr[rslot(2 * u)].x, xr[rslot(2 * u)].y);
+                hf[rslot(2 * u + 1)] =
+                    row_lowpass<LO_R>(A.lo, xr[rslot(2 * u + 1)].x, xr[rslot(2 * u + 1)].y);
+                // lowpass row n - 2 from hf rows 2n - 8 .. 2n
+                float h[2 * LO_R + 1];
+#pragma unroll
+                for (int k = 0; k <= 2 * LO_R; ++k) h[k] = hf[rslot(2 * u - 4 - LO_R + k)];
+                const float cv = col_lowpass<LO_R>(A.lo, h);
+                {
+                    const int s = (S >> 1) + n - 2;
+                    if (own && s >= (rb >> 1) && s < (re >> 1)) cp[int64_t(s) * A.c_out.ld + kc] = cv;
+                }
+                uh[cslot(u - 2)] = row_upsample<UP_R>(A.up, cv);
+                // bandpass rows 2m, 2m + 1 with m = n - 4
+                {
+                    const Pair um2 = uh[cslot(u - 6)], um1 = uh[cslot(u - 5)], u0 = uh[cslot(u - 4)];
+                    const Pair up1 = uh[cslot(u - 3)], up2 = uh[cslot(u - 2)];
+                    const Pair xe = xr[rslot(2 * u - 8)], xo = xr[rslot(2 * u - 7)];
+                    Pair de, dod;
+                    float ex = A.up.t[0] * u0.x, ey = A.up.t[0] * u0.y;
+                    ex = fmaf(A.up.t[2], um1.x + up1.x, ex);
+                    ey = fmaf(A.up.t[2], um1.y + up1.y, ey);
+                    if (UP_R >= 4) {
+                        ex = fmaf(A.up.t[4], um2.x + up2.x, ex);
+                        ey = fmaf(A.up.t[4], um2.y + up2.y, ey);
+                    }
+                    float ox = A.up.t[1] * (u0.x + up1.x), oy = A.up.t[1] * (u0.y + up1.y);
+                    ox = fmaf(A.up.t[3], um1.x + up2.x, ox);
+                    oy = fmaf(A.up.t[3], um1.y + up2.y, oy);
+                    de.x = xe.x - ex;
+                    de.y = xe.y - ey;
+                    dod.x = xo.x - ox;
+                    dod.y = xo.y - oy;
+                    dr[rslot(2 * u - 8)] = de;
+                    dr[rslot(2 * u - 7)] = dod;
+                }
+                // DFB tree level 1 then level 2, step q on rows 2n - 9 - q, 2n - 8 - q
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int st = q & 3;
+                    const float cf = 0.5f * A.L.c[st];
+                    const int par = (FO + st) & 1;
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const int rel = 2 * u - 9 - q + j;          // row parity = (1 + q + j) & 1
+                        const int rpar = (((-9 - q + j) % 2) + 2) % 2;
+                        Pair& X = dr[rslot(rel)];
+                        const Pair& Up = dr[rslot(rel - 1)];
+                        const Pair& Dn = dr[rslot(rel + 1)];
+                        if (q < 4) {
+                            // points with (row + column) & 1 == par
+                            if (rpar == par) X.x = fmaf(cf, (X.y + from_prev(X.y)) - (Dn.x + Up.x), X.x);
+                            else X.y = fmaf(cf, (from_next(X.x) + X.x) - (Dn.y + Up.y), X.y);
+                        } else {
+                            // points with column & 1 == par
+                            if (par == 0)
+                                X.x = fmaf(cf, (Up.y + from_prev(Dn.y)) - (Dn.y + from_prev(Up.y)), X.x);
+                            else
+                                X.y = fmaf(cf, (from_next(Up.x) + Dn.x) - (from_next(Dn.x) + Up.x), X.y);
+                        }
+                    }
+                }
+                // rows 2n - 16 (even) and 2n - 15 (odd) are final: compact row i
+                {
+                    const int i = (S >> 1) + n - (LAG >> 1);
+                    if (i >= (rb >> 1) && i < (re >> 1)) {
+                        const Pair E = dr[rslot(2 * u - 16)], O = dr[rslot(2 * u - 15)];
+                        if (own) {
+                            q0[int64_t(i) * Ch + kc] = s0 * E.y;
+                            q1[int64_t(i) * Ch + kc] = s1 * O.x;
+                        }
+                        const int slot = (i - (rb >> 1)) & (VB - 1);
+                        T[lane * VLD + slot] = s2 * E.x;
+                        T[(64 + lane) * VLD + slot] = s3 * O.y;
+                        if (slot == VB - 1 || i == (re >> 1) - 1) flush(i - slot, slot + 1);
+                    }
+                }
+            }
+        }
+    }
+};
+
+}  // namespace stream
+}  // namespace ct
+
+namespace ct {
+namespace stream {
+
+// DFB tree levels 2 and 1 back to the bandpass image, then the dual LP
+// synthesis, in the same streaming layout (paper section 2.1: perfect
+// reconstruction of the LP and DFB). Per compact row n of the four quarter
+// channels (image rows 2n, 2n + 1):
+//   place the channels on the checkerboard, tree level 2 (4 steps) and
+//   level 1 (4 steps) one row further behind each -> bandpass rows 2n - 8,
+//   2n - 7; hf = horizontal lowpass of those rows; c' = c - vertical
+//   lowpass of hf (lowpass row n - 6); uh = horizontal upsampling of c';
+//   x = d + vertical upsampling of uh: image rows 2n - 16, 2n - 15.
+// The vertical-cone channels are stored transposed; blocks of VB compact
+// rows of them are staged through wave-private LDS (double-buffered, loaded
+// one block ahead).
+template <int LO_R, int UP_R, int NT>
+struct StreamLevelSyn {
+    static constexpr int WAVES = NT / 64;
+    static constexpr int HC = 16;
+    static constexpr int VW = level_cols();
+    static constexpr int TOP = 18;
+    static constexpr int LAG = 16;
+    static constexpr int BH = level_rows();
+    static constexpr int U = 10;             // supersteps per ring cycle
+    static constexpr int RR = 20;            // ring rows: channels / bandpass
+    static constexpr int RH = 10;            // ring rows: hf
+    static constexpr int RC = 5;             // ring rows: uh (lowpass rows)
+    static constexpr int VB = 8;             // compact rows per staged block
+    static constexpr int VLD = VB + 1;
+    static constexpr int BUF = 2 * 64 * VLD; // one staged block, both channels
+    static constexpr int WAVE_SMEM = 2 * BUF;
+    static constexpr int SMEM = WAVES * WAVE_SMEM;
+    static constexpr int NSTAGE = 2 * 64 * VB / 64;   // staging loads per lane per block
+
+    const stage::LevelSynArgs& A;
+    __device__ StreamLevelSyn(const stage::LevelSynArgs& a) : A(a) {}
+
+    static_assert(VW == 128 - 2 * HC, "strip geometry");
+    __device__ int strips() const { return (A.C + VW - 1) / VW; }
+    __device__ int blocks() const { return (A.R + BH - 1) / BH; }
+    __device__ int items() const { return level_items(A.R, A.C, A.batch); }
+    __device__ int tiles() const { return (items() + WAVES - 1) / WAVES; }
+
+    static constexpr int rslot(int rel) { return ((rel % RR) + RR) % RR; }
+    static constexpr int hslot(int rel) { return ((rel % RH) + RH) % RH; }
+    static constexpr int cslot(int rel) { return ((rel % RC) + RC) % RC; }
+
+    __device__ void run_tile(int tile, float* smem) const {
+        const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+        const int item = tile * WAVES + wave;
+        if (item < items()) {
+            float* T = smem + wave * WAVE_SMEM;
+            if (A.L.first_odd) run<1>(item, T);
+            else run<0>(item, T);
+        }
+    }
+
+    template <int FO>
+    __device__ void run(int item, float* T) const {
+        const int ns = strips(), nb = blocks();
+        const int b = item / (ns * nb);
+        const int rem = item - b * ns * nb;
+        const int blk = rem / ns, strip = rem - blk * ns;
+        const int R = A.R, C = A.C, Rh = R >> 1, Ch = C >> 1;
+        const int kb = strip * VW, rb = blk * BH;
+        const int re = min(rb + BH, R);
+        const int lane = threadIdx.x & 63;
+        const int cb0 = kb - HC;
+        const int kcw = pmod((cb0 >> 1) + lane, Ch);     // compact column, wrapped
+        const int S2 = (rb - TOP) >> 1;                  // first streamed compact row
+        const int NS = (re - rb) / 2 + (TOP - 1);
+        const int ow = min(A.out_w, C), oh = min(A.out_h, R);
+        const bool own = lane >= HC / 2 && lane < 64 - HC / 2;
+        const int j0 = cb0 + 2 * lane;                   // image columns j0, j0 + 1
+        const bool st0 = own && j0 < ow, st1 = own && j0 + 1 < ow;
+
+        const float* h0 = A.in.p[0] + b * A.in.plane;    // H a=-1: even rows, odd columns
+        const float* h1 = A.in.p[1] + b * A.in.plane;    // H a=0:  odd rows, even columns
+        const float* v2 = A.in.p[2] + b * A.in.plane;    // V a=0:  even rows, even columns
+        const float* v3 = A.in.p[3] + b * A.in.plane;    // V a=-1: odd rows, odd columns
+        const float s0 = A.in.scale[0], s1 = A.in.scale[1];
+        const float s2 = A.in.scale[2], s3 = A.in.scale[3];
+        const float* cin = A.c_in.p + b * A.c_in.plane;
+        float* xo = A.x_out.p + b * A.x_out.plane;
+
+        // staging of the transposed channels: lane (li, lk) loads compact row
+        // i0 + li of compact columns kk + lk, kk = 0, 4, ..., 60
+        const int li = lane & (VB - 1), lk = lane >> 3;  // VB = 8: 8 columns per load
+        float stg[NSTAGE];
+        auto stage_load = [&](int i0) {
+            const int i = pmod(i0 + li, Rh);
+#pragma unroll
+            for (int c = 0; c < NSTAGE / 2; ++c) {
+                const int k = pmod((cb0 >> 1) + 8 * c + lk, Ch);
+                stg[c] = v2[int64_t(k) * Rh + i];
+                stg[NSTAGE / 2 + c] = v3[int64_t(k) * Rh + i];
+            }
+        };
+        auto stage_store = [&](int buf) {
+            float* B = T + buf * BUF;
+#pragma unroll
+            for (int c = 0; c < NSTAGE / 2; ++c) {
+                const int l = 8 * c + lk;
+                B[l * VLD + li] = stg[c];
+                B[(64 + l) * VLD + li] = stg[NSTAGE / 2 + c];
+            }
+        };
+        auto lds_sync = [&]() {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+
+        int hrow = pmod(S2, Rh);            // next compact row of the H channels
+        int crow = pmod(S2 - 6, Rh);        // next lowpass row
+        Pair hn;                            // prefetched H values of the next compact row
+        float cn;                           // prefetched lowpass value
+        auto load_h = [&]() {
+            hn.x = h1[int64_t(hrow) * Ch + kcw];   // odd row, even column
+            hn.y = h0[int64_t(hrow) * Ch + kcw];   // even row, odd column
+            hrow = hrow + 1 == Rh ? 0 : hrow + 1;
+        };
+        auto load_c = [&]() {
+            cn = cin[int64_t(crow) * A.c_in.ld + kcw];
+            crow = crow + 1 == Rh ? 0 : crow + 1;
+        };
+
+        Pair w[RR];
+        float hf[RH];
+        Pair uh[RC];
+#pragma unroll
+        for (int r = 0; r < RR; ++r) w[r] = Pair{0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < RH; ++r) hf[r] = 0.f;
+#pragma unroll
+        for (int r = 0; r < RC; ++r) uh[r] = Pair{0.f, 0.f};
+
+        // staged block 0 now, block 1 in flight
+        stage_load(S2);
+        stage_store(0);
+        stage_load(S2 + VB);
+        load_h();
+        load_c();
+        for (int n0 = 0; n0 < NS; n0 += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int n = n0 + u;
+                const int nb_ = n / VB, ni = n - nb_ * VB;
+                if (ni == 1) {
+                    // block nb_ + 1 arrives in the other buffer; block nb_ + 2 goes out
+                    stage_store((nb_ + 1) & 1);
+                    stage_load(S2 + (nb_ + 2) * VB);
+                }
+                if (ni == 0) lds_sync();
+                // compact row n onto the checkerboard (image rows 2n, 2n + 1)
+                {
+                    const float* B = T + (nb_ & 1) * BUF;
+                    Pair& E = w[rslot(2 * u)];
+                    Pair& O = w[rslot(2 * u + 1)];
+                    E.x = s2 * B[lane * VLD + ni];
+                    E.y = s0 * hn.y;
+                    O.x = s1 * hn.x;
+                    O.y = s3 * B[(64 + lane) * VLD + ni];
+                }
+                const float cv = cn;
+                load_h();
+                load_c();
+                // tree level 2 (q < 4) then level 1, step q on rows 2n - 1 - q, 2n - q
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int st = q & 3;
+                    const float cf = 0.5f * A.L.c[st];
+                    const int par = (FO + st) & 1;
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const int rel = 2 * u - 1 - q + j;
+                        const int rpar = (((-1 - q + j) % 2) + 2) % 2;
+                        Pair& X = w[rslot(rel)];
+                        const Pair& Up = w[rslot(rel - 1)];
+                        const Pair& Dn = w[rslot(rel + 1)];
+                        if (q < 4) {
+                            if (par == 0)
+                                X.x = fmaf(cf, (Up.y + from_prev(Dn.y)) - (Dn.y + from_prev(Up.y)), X.x);
+                            else
+                                X.y = fmaf(cf, (from_next(Up.x) + Dn.x) - (from_next(Dn.x) + Up.x), X.y);
+                        } else {
+                            if (rpar == par) X.x = fmaf(cf, (X.y + from_prev(X.y)) - (Dn.x + Up.x), X.x);
+                            else X.y = fmaf(cf, (from_next(X.x) + X.x) - (Dn.y + Up.y), X.y);
+                        }
+                    }
+                }
+                // bandpass rows 2n - 8, 2n - 7 are final: their horizontal lowpass
+                hf[hslot(2 * u - 8)] = row_lowpass<LO_R>(A.lo, w[rslot(2 * u - 8)].x, w[rslot(2 * u - 8)].y);
+                hf[hslot(2 * u - 7)] = row_lowpass<LO_R>(A.lo, w[rslot(2 * u - 7)].x, w[rslot(2 * u - 7)].y);
+                // lowpass row n - 6: c' = c - vertical lowpass of hf rows 2n - 12 +- LO_R
+                float h[2 * LO_R + 1];
+#pragma unroll
+                for (int k = 0; k <= 2 * LO_R; ++k) h[k] = hf[hslot(2 * u - 12 - LO_R + k)];
+                const float cp = cv - col_lowpass<LO_R>(A.lo, h);
+                uh[cslot(u - 6)] = row_upsample<UP_R>(A.up, cp);
+                // image rows 2m, 2m + 1 with m = n - 8
+                {
+                    const Pair um2 = uh[cslot(u - 10)], um1 = uh[cslot(u - 9)], u0 = uh[cslot(u - 8)];
+                    const Pair up1 = uh[cslot(u - 7)], up2 = uh[cslot(u - 6)];
+                    const Pair de = w[rslot(2 * u - 16)], dod = w[rslot(2 * u - 15)];
+                    float ex = A.up.t[0] * u0.x, ey = A.up.t[0] * u0.y;
+                    ex = fmaf(A.up.t[2], um1.x + up1.x, ex);
+                    ey = fmaf(A.up.t[2], um1.y + up1.y, ey);
+                    if (UP_R >= 4) {
+                        ex = fmaf(A.up.t[4], um2.x + up2.x, ex);
+                        ey = fmaf(A.up.t[4], um2.y + up2.y, ey);
+                    }
+                    float ox = A.up.t[1] * (u0.x + up1.x), oy = A.up.t[1] * (u0.y + up1.y);
+                    ox = fmaf(A.up.t[3], um1.x + up2.x, ox);
+                    oy = fmaf(A.up.t[3], um1.y + up2.y, oy);
+                    const int r = 2 * S2 + 2 * n - LAG;          // image row of de
+                    if (r >= rb && r < re && r < oh) {
+                        float* rp = xo + int64_t(r) * A.x_out.ld;
+                        if (st0) rp[j0] = de.x + ex;
+                        if (st1) rp[j0 + 1] = de.y + ey;
+                    }
+                    if (r + 1 >= rb && r + 1 < re && r + 1 < oh) {
+                        float* rp = xo + int64_t(r + 1) * A.x_out.ld;
+                        if (st0) rp[j0] = dod.x + ox;
+                        if (st1) rp[j0 + 1] = dod.y + oy;
+                    }
+                }
+            }
+        }
+    }
+};
+
+}  // namespace stream
+}  // namespace ct

@@ -56,7 +56,7 @@ class StreamDesc(ctypes.Structure):
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("streams", ctypes.c_int32), ("stages", ctypes.c_int32),
-                ("work_items", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("work_items", ctypes.c_int32), ("launches", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("autotuned", ctypes.c_int32),
                 ("levels_paired", ctypes.c_int32), ("levels_single", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_int64)]

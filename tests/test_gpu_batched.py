@@ -1,4 +1,4 @@
-"""GPU tests of the batched form (one persistent, graph-captured launch).
+"""GPU tests of the batched form (one graph launch of grouped kernels).
 
 Mixed streams of uneven resolution, LP depth and direction counts run
 forward + quantise + dequantise + inverse in one launch; the result must be
@@ -7,6 +7,7 @@ with the oracle.
 """
 import json
 import os
+import time
 
 import numpy as np
 import pytest
@@ -58,16 +59,20 @@ def test_batched_equals_plain_and_replays():
     print("[batched] graph plan over", len(STREAMS), "streams", flush=True)
     plan = ct.Batched(_streams(), graph=True)
     info = plan.info()
+    print("[batched] plan", info, flush=True)
     assert info["graph"] == 1 and info["streams"] == len(STREAMS)
     plan.run_plain()
     torch.cuda.synchronize()
+    print("[batched] plain launches done", flush=True)
     plain = _snapshot(plan)
     for s in plan.streams:
         for k in ("coeffs", "idx", "side", "deq", "out"):
             s[k].zero_()
     for rep in range(3):
+        t0 = time.perf_counter()
         plan.run()
         torch.cuda.synchronize()
+        print(f"[batched] graph replay {rep}: {1e3 * (time.perf_counter() - t0):.2f} ms", flush=True)
         _same(plain, _snapshot(plan))
         # eager work between replays, then wipe the outputs
         torch.cuda.synchronize()

@@ -99,6 +99,16 @@ def test_quantiser_bit_exact(name, H, W, J, dirs, B):
         assert side_h[b, 0] == s_ref[0] and side_h[b, 1] == s_ref[1]
         d_ref = oq.dequantize32(q_ref, steps[b], s_ref, table)
         np.testing.assert_array_equal(deq_h[b], d_ref)
+    # arrays 4 bytes off a 16-byte boundary take the per-element path
+    n = B * plan.ncoef
+    cbuf = torch.zeros(n + 1, dtype=torch.float32, device="cuda")
+    cbuf[1:] = _dev(c32).reshape(-1)
+    ibuf = torch.zeros(n + 1, dtype=torch.int16, device="cuda")
+    dbuf = torch.zeros(n + 1, dtype=torch.float32, device="cuda")
+    idx_m, side_m = plan.quantize(cbuf[1:].view(B, plan.ncoef), _dev(steps), idx=ibuf[1:].view(B, plan.ncoef))
+    deq_m = plan.dequantize(idx_m, _dev(steps), side_m, out=dbuf[1:].view(B, plan.ncoef))
+    assert torch.equal(idx_m.cpu(), idx.cpu()) and torch.equal(side_m.cpu(), side.cpu())
+    assert torch.equal(deq_m.cpu(), deq.cpu())
     # shared step row (stride 0)
     idx2, _ = plan.quantize(_dev(c32), _dev(steps[0]))
     idx2_h = idx2.cpu().numpy()
