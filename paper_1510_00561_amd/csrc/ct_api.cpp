@@ -155,6 +155,36 @@ int split_groups(int l, int grouping, int* first, int* count) {
 
 namespace ct {
 
+// Wavefronts of the streaming stages resident at once on the current device
+// (about 150 VGPRs each: three per SIMD, four SIMDs per CU), cached per
+// device.
+int resident_waves() {
+    static std::mutex mu;
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 3072;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!cached[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached[dev] = 12 * cus;
+    }
+    return cached[dev];
+}
+
+int level_block_rows(int Rj, int Cj, int batch) {
+    const int strips = (Cj + level_cols() - 1) / level_cols();
+    return block_rows(Rj, strips * batch, resident_waves(), 32, level_max_rows(), 8);
+}
+
+int split_block_rows(const SplitArgs& a, int batch, int levels) {
+    const int t = a.t, vw = stream_cols(levels);
+    const int nrh = a.Rj >> (t - 2), nch = a.Cj >> 1, nrv = a.Cj >> (t - 2), ncv = a.Rj >> 1;
+    const int cols = (1 << (t - 2)) * ((nch + vw - 1) / vw + (ncv + vw - 1) / vw) * batch;
+    return block_rows(nrh > nrv ? nrh : nrv, cols, resident_waves(), 32, stream_max_rows(levels), 4);
+}
+
 // Stage chain of one transform direction (see ct_batched.h). `grouping[j]`
 // selects pairs (2) or single DFB tree levels (1) at LP level j.
 void build_transform_chain(const Geometry& g, int batch, int mode_i, const float* in, float* out,
@@ -215,7 +245,8 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
             a.up = up;
             a.L = L;
             a.batch = batch;
-            d.ntiles = level_stage_tiles(Rj, Cj, batch);
+            a.bh = level_block_rows(Rj, Cj, batch);
+            d.ntiles = level_stage_tiles(Rj, Cj, batch, a.bh);
             d.bytes = 4.0 * batch * (double(a.src_h) * a.src_w + double(Rj / 2) * (Cj / 2) + double(Rj) * Cj);
             push(d);
             int first[4], count[4];
@@ -243,6 +274,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     sa.child = other;
                     sa.child_plane = RC;
                 }
+                sa.bh = split_block_rows(sa, batch, count[gi]);
                 e.ntiles = split_stage_tiles(sa, batch, count[gi]);
                 e.bytes = 8.0 * batch * double(Rj) * Cj;
                 push(e);
@@ -296,6 +328,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     sa.parent = other;
                     sa.parent_plane = RC;
                 }
+                sa.bh = split_block_rows(sa, batch, count[gi]);
                 e.ntiles = split_stage_tiles(sa, batch, count[gi]);
                 e.bytes = 8.0 * batch * double(Rj) * Cj;
                 push(e);
@@ -329,7 +362,8 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
         a.up = up;
         a.L = L;
         a.batch = batch;
-        d.ntiles = level_stage_tiles(Rj, Cj, batch);
+        a.bh = level_block_rows(Rj, Cj, batch);
+        d.ntiles = level_stage_tiles(Rj, Cj, batch, a.bh);
         d.bytes = 4.0 * batch * (double(Rj / 2) * (Cj / 2) + double(Rj) * Cj + double(a.out_h) * a.out_w);
         push(d);
     }
@@ -355,18 +389,9 @@ const char* stage_name(int type) {
 }
 
 hipError_t launch_stage_raw(const StageDesc& d, hipStream_t st) {
-    const int up_r = d.lo_r == 4 ? 3 : 4;
     switch (d.type) {
-        case kStLevelAna: {
-            const stage::LevelAnaArgs& a = d.u.la;
-            return launch_lp_dfb12_analysis(a.src, a.src_h, a.src_w, a.pad_mode, a.R, a.C, a.c_out,
-                                            a.out, a.lo, d.lo_r, a.up, up_r, a.L, d.batch, st);
-        }
-        case kStLevelSyn: {
-            const stage::LevelSynArgs& a = d.u.ls;
-            return launch_dfb12_lp_synthesis(a.in, a.c_in, a.R, a.C, a.x_out, a.out_h, a.out_w,
-                                             a.lo, d.lo_r, a.up, up_r, a.L, d.batch, st);
-        }
+        case kStLevelAna: return launch_level_analysis(d.u.la, d.lo_r, st);
+        case kStLevelSyn: return launch_level_synthesis(d.u.ls, d.lo_r, st);
         case kStSplit1Ana: return launch_dfb_split_analysis(d.u.sp, d.lift, d.batch, st);
         case kStSplit2Ana: return launch_dfb_split2_analysis(d.u.sp, d.lift, d.batch, st);
         case kStSplit1Syn: return launch_dfb_split_synthesis(d.u.sp, d.lift, d.batch, st);

@@ -68,15 +68,33 @@ struct SplitArgs {
     int64_t parent_plane, child_plane;  // plane strides of the two buffers
     float scale[64];    // per child channel (applied on store / load)
     int use_scale;
+    int bh;             // rows per streamed block (multiple of 4), see block_rows()
 };
+
+// Rows per streamed block of a register-streaming stage. A wavefront streams
+// one block, so a launch lasts at least one block's stream: the block is cut
+// short enough that the `col_items` columns of items fill about two rounds
+// of `slots` resident wavefronts, between min_rows and max_rows, a multiple
+// of `align`.
+__host__ __device__ inline int block_rows(int rows, int col_items, int slots, int min_rows,
+                                          int max_rows, int align) {
+    int nb = (rows + max_rows - 1) / max_rows;
+    const int want = (2 * slots + col_items - 1) / col_items;
+    if (want > nb) nb = want;
+    int bh = (rows + nb - 1) / nb;
+    bh = (bh + align - 1) / align * align;
+    if (bh < min_rows) bh = min_rows;
+    if (bh > max_rows) bh = max_rows;
+    return bh;
+}
 
 // Work decomposition of the register-streaming split stages (one or two tree
 // levels per pass): every wavefront stores a strip of stream_cols() sheared
-// columns by stream_rows() rows of one parent channel, and loads a halo of
+// columns by SplitArgs::bh rows of one parent channel, and loads a halo of
 // stream_halo() rows and columns around it.
 __host__ __device__ constexpr int stream_halo(int levels) { return levels == 1 ? 4 : 12; }
 __host__ __device__ constexpr int stream_cols(int levels) { return 128 - 2 * stream_halo(levels); }
-__host__ __device__ constexpr int stream_rows(int levels) { return levels == 1 ? 248 : 216; }
+__host__ __device__ constexpr int stream_max_rows(int levels) { return levels == 1 ? 248 : 216; }
 
 // Per plane: horizontal parents first (each with `ih` items, `sh` strips
 // across), then vertical ones (`iv`, `sv`).
@@ -84,7 +102,7 @@ struct StreamCounts {
     int nh, ih, iv, sh, sv;
 };
 __host__ __device__ inline StreamCounts stream_counts(const SplitArgs& a, int levels) {
-    const int t = a.t, vw = stream_cols(levels), bh = stream_rows(levels);
+    const int t = a.t, vw = stream_cols(levels), bh = a.bh;
     const int nrh = a.Rj >> (t - 2), nch = a.Cj >> 1;
     const int nrv = a.Cj >> (t - 2), ncv = a.Rj >> 1;
     StreamCounts c;
@@ -101,12 +119,12 @@ __host__ __device__ inline int stream_items(const SplitArgs& a, int batch, int l
 }
 
 // Work decomposition of the register-streaming LP-level stages: every
-// wavefront stores a strip of level_cols() image columns by level_rows()
-// rows of one plane.
+// wavefront stores a strip of level_cols() image columns by `bh` rows (a
+// multiple of 8, at most level_max_rows()) of one plane.
 __host__ __device__ constexpr int level_cols() { return 96; }
-__host__ __device__ constexpr int level_rows() { return 256; }
-__host__ __device__ inline int level_items(int R, int C, int batch) {
-    return ((C + level_cols() - 1) / level_cols()) * ((R + level_rows() - 1) / level_rows()) * batch;
+__host__ __device__ constexpr int level_max_rows() { return 256; }
+__host__ __device__ inline int level_items(int R, int C, int batch, int bh) {
+    return ((C + level_cols() - 1) / level_cols()) * ((R + bh - 1) / bh) * batch;
 }
 
 hipError_t launch_dfb_split_analysis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
@@ -116,18 +134,6 @@ hipError_t launch_dfb_split_synthesis(const SplitArgs& a, Lift lift, int batch, 
 // at level t+1 (stored back to back in subband order), and back.
 hipError_t launch_dfb_split2_analysis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
 hipError_t launch_dfb_split2_synthesis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
-
-// Fused LP level + DFB tree levels 1-2 (64 x 64 tiles, 16-pixel halo).
-// Analysis: src (c_{j-1}, or the frame on level 1 with pad_mode) -> c_out
-// (the lowpass c_j) and the four tree-level-2 channels `out`.
-hipError_t launch_lp_dfb12_analysis(CView src, int src_h, int src_w, int pad_mode, int R, int C,
-                                    View c_out, Quad out, Taps5 lo, int lo_r, Taps5 up, int up_r,
-                                    Lift lift, int batch, hipStream_t s);
-// Synthesis: the four channels `in` and the lowpass c_in -> x_out (rows <
-// out_h, cols < out_w of the R x C result).
-hipError_t launch_dfb12_lp_synthesis(Quad in, CView c_in, int R, int C, View x_out, int out_h,
-                                     int out_w, Taps5 lo, int lo_r, Taps5 up, int up_r, Lift lift,
-                                     int batch, hipStream_t s);
 
 // Folds the mirrored padding back onto its sources (transpose of padding):
 // out[r][c] = sum of in[r'][c'] over r' in {r, 2H-1-r}, c' in {c, 2W-1-c}

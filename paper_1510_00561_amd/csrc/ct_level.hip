@@ -59,40 +59,29 @@ __global__ __launch_bounds__(256) void pad_fold_kernel(CView in, int R, int C, V
 
 }  // namespace
 
-hipError_t launch_lp_dfb12_analysis(CView src, int src_h, int src_w, int pad_mode, int R, int C,
-                                    View c_out, Quad out, Taps5 lo, int lo_r, Taps5 up, int up_r,
-                                    Lift lift, int batch, hipStream_t st) {
-    stage::LevelAnaArgs a{src, src_h, src_w, pad_mode, R, C, c_out, out, lo, up, lift, batch};
+hipError_t launch_level_analysis(const stage::LevelAnaArgs& a, int lo_r, hipStream_t st) {
+    if (a.bh <= 0 || (a.bh & 7)) return hipErrorInvalidValue;
     constexpr int waves = NT_STREAM / 64;
-    const int tiles = (level_items(R, C, batch) + waves - 1) / waves;
-    if (lo_r == 4 && up_r == 3) {
-        stream_level_analysis_kernel<4, 3><<<tiles, NT_STREAM, 0, st>>>(a);
-    } else if (lo_r == 3 && up_r == 4) {
-        stream_level_analysis_kernel<3, 4><<<tiles, NT_STREAM, 0, st>>>(a);
-    } else {
-        return hipErrorInvalidValue;
-    }
+    const int tiles = (level_items(a.R, a.C, a.batch, a.bh) + waves - 1) / waves;
+    if (lo_r == 4) stream_level_analysis_kernel<4, 3><<<tiles, NT_STREAM, 0, st>>>(a);
+    else if (lo_r == 3) stream_level_analysis_kernel<3, 4><<<tiles, NT_STREAM, 0, st>>>(a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_dfb12_lp_synthesis(Quad in, CView c_in, int R, int C, View x_out, int out_h,
-                                     int out_w, Taps5 lo, int lo_r, Taps5 up, int up_r, Lift lift,
-                                     int batch, hipStream_t st) {
-    stage::LevelSynArgs a{in, c_in, R, C, x_out, out_h, out_w, lo, up, lift, batch};
+hipError_t launch_level_synthesis(const stage::LevelSynArgs& a, int lo_r, hipStream_t st) {
+    if (a.bh <= 0 || (a.bh & 7)) return hipErrorInvalidValue;
     constexpr int waves = NT_STREAM / 64;
-    const int tiles = (level_items(R, C, batch) + waves - 1) / waves;
-    if (lo_r == 4 && up_r == 3) {
-        stream_level_synthesis_kernel<4, 3><<<tiles, NT_STREAM, 0, st>>>(a);
-    } else if (lo_r == 3 && up_r == 4) {
-        stream_level_synthesis_kernel<3, 4><<<tiles, NT_STREAM, 0, st>>>(a);
-    } else {
-        return hipErrorInvalidValue;
-    }
+    const int tiles = (level_items(a.R, a.C, a.batch, a.bh) + waves - 1) / waves;
+    if (lo_r == 4) stream_level_synthesis_kernel<4, 3><<<tiles, NT_STREAM, 0, st>>>(a);
+    else if (lo_r == 3) stream_level_synthesis_kernel<3, 4><<<tiles, NT_STREAM, 0, st>>>(a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 template <int LEVELS, bool ANA>
 static hipError_t launch_split(const SplitArgs& a, Lift lift, int batch, hipStream_t st) {
+    if (a.bh <= 0 || (a.bh & 3)) return hipErrorInvalidValue;
     constexpr int waves = NT_STREAM / 64;
     const int tiles = (stream_items(a, batch, LEVELS) + waves - 1) / waves;
     stream_split_kernel<LEVELS, ANA><<<tiles, NT_STREAM, 0, st>>>(a, lift, batch);

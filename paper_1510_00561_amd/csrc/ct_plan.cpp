@@ -134,6 +134,7 @@ float time_level_splits(int Rj, int Cj, int l, int batch, int grouping, float* A
             a.child = gi == ng - 1 ? D : other;
             a.child_plane = plane;
             a.plane_elems = int64_t(Rj) * Cj;
+            a.bh = split_block_rows(a, batch, count[gi]);
             hipError_t e = count[gi] == 2 ? launch_dfb_split2_analysis(a, L, batch, st)
                                           : launch_dfb_split_analysis(a, L, batch, st);
             if (e != hipSuccess) return false;
@@ -152,6 +153,7 @@ float time_level_splits(int Rj, int Cj, int l, int batch, int grouping, float* A
             a.child = cur2;
             a.child_plane = plane;
             a.plane_elems = int64_t(Rj) * Cj;
+            a.bh = split_block_rows(a, batch, count[gi]);
             hipError_t e = count[gi] == 2 ? launch_dfb_split2_synthesis(a, L, batch, st)
                                           : launch_dfb_split_synthesis(a, L, batch, st);
             if (e != hipSuccess) return false;

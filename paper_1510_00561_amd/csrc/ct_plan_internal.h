@@ -42,12 +42,16 @@ int build_dequant_chain(const Geometry& g, int batch, const int16_t* idx, const 
 int launch_stage(const StageDesc& d, hipStream_t st);
 int launch_chain(const std::vector<StageDesc>& chain, hipStream_t st);
 int fill_quant_args(const Geometry& g, QuantArgs* a);
+int resident_waves();
+// Rows per streamed block of an LP-level stage and of a split stage.
+int level_block_rows(int Rj, int Cj, int batch);
+int split_block_rows(const SplitArgs& a, int batch, int levels);
 
 // Work-queue tiles of an LP-level stage (one wavefront item per strip and
 // row block, kBatchedThreads / 64 per tile).
-inline int level_stage_tiles(int R, int C, int batch) {
+inline int level_stage_tiles(int R, int C, int batch, int bh) {
     constexpr int waves = kBatchedThreads / 64;
-    return (level_items(R, C, batch) + waves - 1) / waves;
+    return (level_items(R, C, batch, bh) + waves - 1) / waves;
 }
 
 // Work-queue tiles of a DFB split stage covering `levels` (1 or 2) tree

@@ -20,6 +20,7 @@ struct LevelAnaArgs {
     Taps5 lo, up;
     Lift L;
     int batch;
+    int bh;                 // rows per streamed block, a multiple of 8
 };
 
 // DFB tree levels 1-2 + LP level, synthesis: the four channels `in` and the
@@ -33,6 +34,7 @@ struct LevelSynArgs {
     Taps5 lo, up;
     Lift L;
     int batch;
+    int bh;                 // rows per streamed block, a multiple of 8
 };
 
 // Geometry of a parent channel at tree level t-1 (split at level t).
@@ -77,4 +79,10 @@ __device__ __forceinline__ int grandchild_pos(bool vertical, int pp, int cls) {
 }
 
 }  // namespace stage
+
+// Per-stage launches of the LP-level stages (`lo_r` = reach of the lowpass
+// filter: 4 for hbar, 3 for gbar in the transposes).
+hipError_t launch_level_analysis(const stage::LevelAnaArgs& a, int lo_r, hipStream_t s);
+hipError_t launch_level_synthesis(const stage::LevelSynArgs& a, int lo_r, hipStream_t s);
+
 }  // namespace ct

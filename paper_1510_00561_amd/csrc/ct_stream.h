@@ -33,15 +33,14 @@
 namespace ct {
 namespace stream {
 
-// lane l receives lane l + 1's value (wavefront shift; the last lane gets 0)
+// lane l receives lane l + 1's value (wavefront shift; bound_ctrl makes the
+// last lane read 0, so no old value has to be set up)
 __device__ __forceinline__ float from_next(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                 0x130, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
 }
-// lane l receives lane l - 1's value (the first lane gets 0)
+// lane l receives lane l - 1's value (the first lane reads 0)
 __device__ __forceinline__ float from_prev(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                 0x138, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
 }
 
 struct Pair {
@@ -76,7 +75,6 @@ struct StreamSplit {
     static constexpr int TL = stream_halo(LEVELS);         // total lag = halo rows = halo columns
     static constexpr int HC = TL;
     static constexpr int VW = stream_cols(LEVELS);         // stored columns per strip
-    static constexpr int BH = stream_rows(LEVELS);         // stored rows per block
     static constexpr int RING = LEVELS == 1 ? 16 : 24;     // ring rows (multiple of 4)
     static constexpr int UNROLL = RING / 4;
     static constexpr int NSTEP = 4 * LEVELS;
@@ -137,8 +135,8 @@ struct StreamSplit {
         }
         const stage::SplitGeom g = stage::split_geom(A, pp);
         const int nr = g.nr, nc = g.nc;
-        const int kb = strip * VW, rb = blk * BH;
-        const int ke = min(kb + VW, nc), re = min(rb + BH, nr);
+        const int kb = strip * VW, rb = blk * A.bh;
+        const int ke = min(kb + VW, nc), re = min(rb + A.bh, nr);
         const int lane = threadIdx.x & 63;
         // byte offsets of the lane's two columns modulo the row, relative to
         // the row's column base (kb - HC - a i) mod nc

@@ -76,7 +76,6 @@ struct StreamLevelAna {
     static constexpr int VW = level_cols();  // stored image columns per strip (128 - 2 HC)
     static constexpr int TOP = 18;           // rows loaded above a block
     static constexpr int LAG = 16;           // rows from the newest loaded row to the output
-    static constexpr int BH = level_rows();  // stored image rows per block
     static constexpr int U = 6;              // supersteps per ring cycle
     static constexpr int RR = 12;            // ring rows: x, hf and d
     static constexpr int RC = 6;             // ring rows: uh (lowpass rows)
@@ -90,8 +89,8 @@ struct StreamLevelAna {
 
     static_assert(VW == 128 - 2 * HC, "strip geometry");
     __device__ int strips() const { return (A.C + VW - 1) / VW; }
-    __device__ int blocks() const { return (A.R + BH - 1) / BH; }
-    __device__ int items() const { return level_items(A.R, A.C, A.batch); }
+    __device__ int blocks() const { return (A.R + A.bh - 1) / A.bh; }
+    __device__ int items() const { return level_items(A.R, A.C, A.batch, A.bh); }
     __device__ int tiles() const { return (items() + WAVES - 1) / WAVES; }
 
     static constexpr int rslot(int rel) { return ((rel % RR) + RR) % RR; }
@@ -114,8 +113,8 @@ struct StreamLevelAna {
         const int rem = item - b * ns * nb;
         const int blk = rem / ns, strip = rem - blk * ns;
         const int R = A.R, C = A.C, Rh = R >> 1, Ch = C >> 1;
-        const int kb = strip * VW, rb = blk * BH;
-        const int re = min(rb + BH, R);
+        const int kb = strip * VW, rb = blk * A.bh;
+        const int re = min(rb + A.bh, R);
         const int lane = threadIdx.x & 63;
         const int cb0 = kb - HC;                    // image column of lane 0's x0 (even)
         const int kc = (cb0 >> 1) + lane;           // this lane's compact column (unwrapped)
@@ -127,7 +126,7 @@ struct StreamLevelAna {
         // padded past the real frame); zero padding clears the loaded bits
         // with a mask, so every load is unconditional
         const float* sp = A.src.p + b * A.src.plane;
-        int sc[2];
+        uint32_t sc[2];                             // byte offsets within a source row
         uint32_t mc[2];
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
@@ -138,7 +137,7 @@ struct StreamLevelAna {
                 mc[e] = 0u;
                 g = 0;
             }
-            sc[e] = g;
+            sc[e] = 4u * uint32_t(g);
         }
         int xrow = pmod(S, R);                      // next row to load, modulo R
         auto load_row = [&](Pair& X) {
@@ -149,9 +148,9 @@ struct StreamLevelAna {
                 mr = 0u;
                 g = 0;
             }
-            const float* rp = sp + int64_t(g) * A.src.ld;
-            X.x = __uint_as_float(__float_as_uint(rp[sc[0]]) & (mr & mc[0]));
-            X.y = __uint_as_float(__float_as_uint(rp[sc[1]]) & (mr & mc[1]));
+            const char* rp = reinterpret_cast<const char*>(sp + int64_t(g) * A.src.ld);
+            X.x = __uint_as_float(*reinterpret_cast<const uint32_t*>(rp + sc[0]) & (mr & mc[0]));
+            X.y = __uint_as_float(*reinterpret_cast<const uint32_t*>(rp + sc[1]) & (mr & mc[1]));
             xrow = xrow + 1 == R ? 0 : xrow + 1;
         };
 
@@ -304,35 +303,36 @@ namespace stream {
 //   2n - 7; hf = horizontal lowpass of those rows; c' = c - vertical
 //   lowpass of hf (lowpass row n - 6); uh = horizontal upsampling of c';
 //   x = d + vertical upsampling of uh: image rows 2n - 16, 2n - 15.
-// The vertical-cone channels are stored transposed; blocks of VB compact
-// rows of them are staged through wave-private LDS (double-buffered, loaded
-// one block ahead).
+// The vertical-cone channels are stored transposed; blocks of VB = 16
+// compact rows of them are staged through wave-private LDS. A block's loads
+// are issued into registers when the previous block starts and written to
+// LDS when their own block starts; aligned blocks that do not wrap are read
+// as 16-byte pieces (four lanes per 64-byte column run).
 template <int LO_R, int UP_R, int NT>
 struct StreamLevelSyn {
     static constexpr int WAVES = NT / 64;
     static constexpr int HC = 16;
     static constexpr int VW = level_cols();
-    static constexpr int TOP = 18;
+    static constexpr int TOP = 16;           // an output row depends on input rows 15 above it
     static constexpr int LAG = 16;
-    static constexpr int BH = level_rows();
     static constexpr int U = 10;             // supersteps per ring cycle
     static constexpr int RR = 20;            // ring rows: channels / bandpass
     static constexpr int RH = 10;            // ring rows: hf
     static constexpr int RC = 5;             // ring rows: uh (lowpass rows)
-    static constexpr int VB = 8;             // compact rows per staged block
+    static constexpr int VB = 16;            // compact rows per staged block
     static constexpr int VLD = VB + 1;
     static constexpr int BUF = 2 * 64 * VLD; // one staged block, both channels
-    static constexpr int WAVE_SMEM = 2 * BUF;
+    static constexpr int WAVE_SMEM = BUF;
     static constexpr int SMEM = WAVES * WAVE_SMEM;
-    static constexpr int NSTAGE = 2 * 64 * VB / 64;   // staging loads per lane per block
+    static constexpr int NSTAGE = 2 * 64 * VB / 64;   // staged values per lane per block
 
     const stage::LevelSynArgs& A;
     __device__ StreamLevelSyn(const stage::LevelSynArgs& a) : A(a) {}
 
     static_assert(VW == 128 - 2 * HC, "strip geometry");
     __device__ int strips() const { return (A.C + VW - 1) / VW; }
-    __device__ int blocks() const { return (A.R + BH - 1) / BH; }
-    __device__ int items() const { return level_items(A.R, A.C, A.batch); }
+    __device__ int blocks() const { return (A.R + A.bh - 1) / A.bh; }
+    __device__ int items() const { return level_items(A.R, A.C, A.batch, A.bh); }
     __device__ int tiles() const { return (items() + WAVES - 1) / WAVES; }
 
     static constexpr int rslot(int rel) { return ((rel % RR) + RR) % RR; }
@@ -356,13 +356,13 @@ struct StreamLevelSyn {
         const int rem = item - b * ns * nb;
         const int blk = rem / ns, strip = rem - blk * ns;
         const int R = A.R, C = A.C, Rh = R >> 1, Ch = C >> 1;
-        const int kb = strip * VW, rb = blk * BH;
-        const int re = min(rb + BH, R);
+        const int kb = strip * VW, rb = blk * A.bh;
+        const int re = min(rb + A.bh, R);
         const int lane = threadIdx.x & 63;
         const int cb0 = kb - HC;
         const int kcw = pmod((cb0 >> 1) + lane, Ch);     // compact column, wrapped
-        const int S2 = (rb - TOP) >> 1;                  // first streamed compact row
-        const int NS = (re - rb) / 2 + (TOP - 1);
+        const int S2 = (rb - TOP) >> 1;                  // first streamed compact row (0 mod 4)
+        const int NS = (re - rb) / 2 + (TOP + LAG) / 2;  // the first output pair leaves at n = 16
         const int ow = min(A.out_w, C), oh = min(A.out_h, R);
         const bool own = lane >= HC / 2 && lane < 64 - HC / 2;
         const int j0 = cb0 + 2 * lane;                   // image columns j0, j0 + 1
@@ -377,26 +377,55 @@ struct StreamLevelSyn {
         const float* cin = A.c_in.p + b * A.c_in.plane;
         float* xo = A.x_out.p + b * A.x_out.plane;
 
-        // staging of the transposed channels: lane (li, lk) loads compact row
-        // i0 + li of compact columns kk + lk, kk = 0, 4, ..., 60
-        const int li = lane & (VB - 1), lk = lane >> 3;  // VB = 8: 8 columns per load
+        // Staging of the transposed channels, compact rows [i0, i0 + 16) of the
+        // strip's 64 compact columns: lane (cg, rc) holds rows i0 + 4 rc .. + 3
+        // of columns 16 c + cg, c = 0..3. Blocks aligned to 4 rows and inside
+        // the array are read as one 16-byte load per column; wrapping or
+        // unaligned blocks element by element.
+        const bool vec_ok = (Rh & 3) == 0 &&
+                            ((reinterpret_cast<uintptr_t>(v2) | reinterpret_cast<uintptr_t>(v3)) & 15) == 0;
+        const int cg = lane >> 2, rc = lane & 3;
+        int64_t kcol[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) kcol[c] = int64_t(pmod((cb0 >> 1) + 16 * c + cg, Ch)) * Rh;
         float stg[NSTAGE];
         auto stage_load = [&](int i0) {
-            const int i = pmod(i0 + li, Rh);
+            if (vec_ok && i0 >= 0 && i0 + VB <= Rh) {
 #pragma unroll
-            for (int c = 0; c < NSTAGE / 2; ++c) {
-                const int k = pmod((cb0 >> 1) + 8 * c + lk, Ch);
-                stg[c] = v2[int64_t(k) * Rh + i];
-                stg[NSTAGE / 2 + c] = v3[int64_t(k) * Rh + i];
+                for (int c = 0; c < 4; ++c) {
+                    const int64_t o = kcol[c] + i0 + 4 * rc;
+                    const float4 a = *reinterpret_cast<const float4*>(v2 + o);
+                    const float4 e = *reinterpret_cast<const float4*>(v3 + o);
+                    stg[4 * c + 0] = a.x;
+                    stg[4 * c + 1] = a.y;
+                    stg[4 * c + 2] = a.z;
+                    stg[4 * c + 3] = a.w;
+                    stg[16 + 4 * c + 0] = e.x;
+                    stg[16 + 4 * c + 1] = e.y;
+                    stg[16 + 4 * c + 2] = e.z;
+                    stg[16 + 4 * c + 3] = e.w;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int i = pmod(i0 + 4 * rc + e, Rh);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        stg[4 * c + e] = v2[kcol[c] + i];
+                        stg[16 + 4 * c + e] = v3[kcol[c] + i];
+                    }
+                }
             }
         };
-        auto stage_store = [&](int buf) {
-            float* B = T + buf * BUF;
+        auto stage_store = [&]() {
+            float* Tl = T + cg * VLD + 4 * rc;
 #pragma unroll
-            for (int c = 0; c < NSTAGE / 2; ++c) {
-                const int l = 8 * c + lk;
-                B[l * VLD + li] = stg[c];
-                B[(64 + l) * VLD + li] = stg[NSTAGE / 2 + c];
+            for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    Tl[16 * c * VLD + e] = stg[4 * c + e];
+                    Tl[(64 + 16 * c) * VLD + e] = stg[16 + 4 * c + e];
+                }
             }
         };
         auto lds_sync = [&]() {
@@ -429,9 +458,10 @@ struct StreamLevelSyn {
 #pragma unroll
         for (int r = 0; r < RC; ++r) uh[r] = Pair{0.f, 0.f};
 
-        // staged block 0 now, block 1 in flight
+        // block 0 staged now, block 1 in flight
         stage_load(S2);
-        stage_store(0);
+        stage_store();
+        lds_sync();
         stage_load(S2 + VB);
         load_h();
         load_c();
@@ -440,21 +470,22 @@ struct StreamLevelSyn {
             for (int u = 0; u < U; ++u) {
                 const int n = n0 + u;
                 const int nb_ = n / VB, ni = n - nb_ * VB;
-                if (ni == 1) {
-                    // block nb_ + 1 arrives in the other buffer; block nb_ + 2 goes out
-                    stage_store((nb_ + 1) & 1);
-                    stage_load(S2 + (nb_ + 2) * VB);
+                if (ni == 0 && nb_ > 0) {
+                    // block nb_ (loaded one block ago) replaces block nb_ - 1;
+                    // block nb_ + 1 goes out
+                    lds_sync();
+                    stage_store();
+                    lds_sync();
+                    stage_load(S2 + (nb_ + 1) * VB);
                 }
-                if (ni == 0) lds_sync();
                 // compact row n onto the checkerboard (image rows 2n, 2n + 1)
                 {
-                    const float* B = T + (nb_ & 1) * BUF;
                     Pair& E = w[rslot(2 * u)];
                     Pair& O = w[rslot(2 * u + 1)];
-                    E.x = s2 * B[lane * VLD + ni];
+                    E.x = s2 * T[lane * VLD + ni];
                     E.y = s0 * hn.y;
                     O.x = s1 * hn.x;
-                    O.y = s3 * B[(64 + lane) * VLD + ni];
+                    O.y = s3 * T[(64 + lane) * VLD + ni];
                 }
                 const float cv = cn;
                 load_h();
