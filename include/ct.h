@@ -169,6 +169,29 @@ int ct_dequantize(const ct_geom* geom, int32_t batch, const int16_t* idx, const 
                   int32_t steps_stride, const float* side, float* coeffs, hipStream_t stream);
 
 /*
+ * Fused encoder and decoder: the same computations as ct_forward followed by
+ * ct_quantize, and ct_dequantize followed by ct_inverse, with the float
+ * coefficients kept out of HBM (paper section 3: the CT feeds the quantiser
+ * directly, and the decoder the inverse CT).
+ * ct_encode rounds every directional coefficient to its index where the DFB
+ * produces it, with the quantiser's float32 operations on the value that
+ * ct_forward would store, then quantises the lowpass (which needs its plane
+ * min/max first) in two small passes. Its idx and side equal those of
+ * ct_forward + ct_quantize bit for bit. `coeffs` may be NULL; when given it
+ * also receives the float coefficients of ct_forward.
+ * ct_decode dequantises where the inverse CT loads the subbands and the
+ * lowpass, with ct_dequantize's float32 operations; its output equals
+ * ct_dequantize + ct_inverse bit for bit.
+ * Arguments and workspace as for the separate calls.
+ */
+int ct_encode(const ct_geom* geom, int32_t batch, const float* planes, const float* steps,
+              int32_t steps_stride, int16_t* idx, float* side, float* coeffs,
+              void* ws, size_t ws_bytes, hipStream_t stream);
+int ct_decode(const ct_geom* geom, int32_t batch, const int16_t* idx, const float* steps,
+              int32_t steps_stride, const float* side, float* planes,
+              void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * Transposes for the differentiable form (gradients through the CT).
  * ct_forward_adjoint computes F^T g: gcoeffs [batch][ncoef] -> gplanes [batch][H][W].
  * ct_inverse_adjoint computes S^T g: gplanes [batch][H][W] -> gcoeffs [batch][ncoef].

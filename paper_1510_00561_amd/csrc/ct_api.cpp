@@ -185,11 +185,22 @@ int split_block_rows(const SplitArgs& a, int batch, int levels) {
     return block_rows(nrh > nrv ? nrh : nrv, cols, resident_waves(), 32, stream_max_rows(levels), 4);
 }
 
+// Subband index of the first subband of LP level j in the coefficient layout
+// (lowpass first, then levels J..1).
+static int first_subband(const Geometry& g, int j) {
+    int s = 1;
+    for (int i = g.J; i > j; --i) s += g.dirs[i - 1];
+    return s;
+}
+
 // Stage chain of one transform direction (see ct_batched.h). `grouping[j]`
-// selects pairs (2) or single DFB tree levels (1) at LP level j.
+// selects pairs (2) or single DFB tree levels (1) at LP level j. With `fq`
+// the final subbands are quantised where the forward transform produces
+// them, or dequantised where the inverse consumes them (the fused encoder
+// and decoder); the float coefficients `out` / `in` may then be null.
 void build_transform_chain(const Geometry& g, int batch, int mode_i, const float* in, float* out,
                            char* ws, const Workspace& w, const int* grouping,
-                           std::vector<StageDesc>& chain) {
+                           std::vector<StageDesc>& chain, const FusedQuant* fq) {
     const Mode mode = Mode(mode_i);
     const bool analysis = mode == Mode::Forward || mode == Mode::InverseAdjoint;
     const bool plain_filters = mode == Mode::Forward || mode == Mode::Inverse;
@@ -226,28 +237,39 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                 a.src_w = Cj;
                 a.pad_mode = kPadNone;
             }
-            a.c_out = (j == g.J)
-                          ? View{coeffs, g.ncoef, Cj / 2}
-                          : View{reinterpret_cast<float*>(ws + w.c_off[j]), int64_t(Rj / 2) * (Cj / 2), Cj / 2};
+            if (j < g.J)
+                a.c_out = View{reinterpret_cast<float*>(ws + w.c_off[j]), int64_t(Rj / 2) * (Cj / 2), Cj / 2};
+            else if (coeffs)
+                a.c_out = View{coeffs, g.ncoef, Cj / 2};
+            else    // fused encoder without float coefficients: the lowpass in the workspace
+                a.c_out = View{reinterpret_cast<float*>(ws + w.low_off), g.low_n, Cj / 2};
             a.R = Rj;
             a.C = Cj;
             const int l = g.l[j - 1];
-            float* level = coeffs + g.level_off[j];
+            float* level = coeffs ? coeffs + g.level_off[j] : nullptr;
             const int64_t q4 = int64_t(Rj) * Cj / 4;
+            const QuantIO qio = fq ? QuantIO{fq->idx + g.level_off[j], g.ncoef, fq->steps, fq->steps_stride,
+                                             first_subband(g, j)}
+                                   : QuantIO{nullptr, 0, nullptr, 0, 0};
             float sc[kMaxDirs];
             scale_table(l, mode == Mode::Forward ? +1 : -1, sc);
             for (int k = 0; k < 4; ++k) {
-                a.out.p[k] = (l == 2 ? level : A) + k * q4;
+                a.out.p[k] = l == 2 ? (level ? level + k * q4 : nullptr) : A + k * q4;
                 a.out.scale[k] = l == 2 ? sc[k] : 1.f;
             }
             a.out.plane = l == 2 ? g.ncoef : RC;
+            if (l == 2) a.q = qio;
             a.lo = lo;
             a.up = up;
             a.L = L;
             a.batch = batch;
             a.bh = level_block_rows(Rj, Cj, batch);
             d.ntiles = level_stage_tiles(Rj, Cj, batch, a.bh);
-            d.bytes = 4.0 * batch * (double(a.src_h) * a.src_w + double(Rj / 2) * (Cj / 2) + double(Rj) * Cj);
+            // compulsory bytes: input, lowpass, the four channels (indices
+            // and / or floats when they are the final subbands)
+            const double chan = l == 2 ? (level ? 4.0 : 0.0) + (qio.idx ? 2.0 : 0.0) : 4.0;
+            d.bytes = batch * (4.0 * double(a.src_h) * a.src_w + 4.0 * double(Rj / 2) * (Cj / 2) +
+                               chan * double(Rj) * Cj);
             push(d);
             int first[4], count[4];
             const int ng = split_groups(l, grouping[j - 1], first, count);
@@ -270,13 +292,15 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     sa.child_plane = g.ncoef;
                     sa.use_scale = 1;
                     memcpy(sa.scale, sc, sizeof(float) * (1 << l));
+                    sa.q = qio;
                 } else {
                     sa.child = other;
                     sa.child_plane = RC;
                 }
                 sa.bh = split_block_rows(sa, batch, count[gi]);
                 e.ntiles = split_stage_tiles(sa, batch, count[gi]);
-                e.bytes = 8.0 * batch * double(Rj) * Cj;
+                const double out_b = last ? (level ? 4.0 : 0.0) + (qio.idx ? 2.0 : 0.0) : 4.0;
+                e.bytes = batch * (4.0 + out_b) * double(Rj) * Cj;
                 push(e);
                 float* tmp = cur;
                 cur = other;
@@ -289,8 +313,11 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
     for (int j = g.J; j >= 1; --j) {
         const int Rj = g.R >> (j - 1), Cj = g.C >> (j - 1);
         const int l = g.l[j - 1];
-        const float* level = coeffs + g.level_off[j];
+        const float* level = coeffs ? coeffs + g.level_off[j] : nullptr;
         const int64_t q4 = int64_t(Rj) * Cj / 4;
+        const QuantIO qio = fq ? QuantIO{const_cast<int16_t*>(fq->idx) + g.level_off[j], g.ncoef, fq->steps,
+                                         fq->steps_stride, first_subband(g, j)}
+                               : QuantIO{nullptr, 0, nullptr, 0, 0};
         float sc[kMaxDirs];
         scale_table(l, mode == Mode::Inverse ? -1 : +1, sc);
         StageDesc d;
@@ -299,10 +326,11 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
         stage::LevelSynArgs& a = d.u.ls;
         if (l == 2) {
             for (int k = 0; k < 4; ++k) {
-                a.in.p[k] = const_cast<float*>(level) + k * q4;
+                a.in.p[k] = level ? const_cast<float*>(level) + k * q4 : nullptr;
                 a.in.scale[k] = sc[k];
             }
             a.in.plane = g.ncoef;
+            a.q = qio;
         } else {
             int first[4], count[4];
             const int ng = split_groups(l, grouping[j - 1], first, count);
@@ -324,13 +352,15 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     sa.parent_plane = g.ncoef;
                     sa.use_scale = 1;
                     memcpy(sa.scale, sc, sizeof(float) * (1 << l));
+                    sa.q = qio;
                 } else {
                     sa.parent = other;
                     sa.parent_plane = RC;
                 }
                 sa.bh = split_block_rows(sa, batch, count[gi]);
                 e.ntiles = split_stage_tiles(sa, batch, count[gi]);
-                e.bytes = 8.0 * batch * double(Rj) * Cj;
+                const double in_b = (gi == ng - 1 && qio.idx) ? 2.0 : 4.0;
+                e.bytes = batch * (in_b + 4.0) * double(Rj) * Cj;
                 push(e);
                 float* tmp = cur;
                 cur = other;
@@ -345,6 +375,11 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
         a.c_in = (j == g.J)
                      ? CView{coeffs, g.ncoef, Cj / 2}
                      : CView{reinterpret_cast<const float*>(ws + w.c_off[j]), int64_t(Rj / 2) * (Cj / 2), Cj / 2};
+        if (j == g.J && fq) {
+            // fused decoder: the lowpass indices, dequantised on load
+            a.lq = QuantIO{const_cast<int16_t*>(fq->idx), g.ncoef, fq->steps, fq->steps_stride, 0};
+            a.side = fq->side;
+        }
         a.R = Rj;
         a.C = Cj;
         a.out_h = Rj;
@@ -364,7 +399,10 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
         a.batch = batch;
         a.bh = level_block_rows(Rj, Cj, batch);
         d.ntiles = level_stage_tiles(Rj, Cj, batch, a.bh);
-        d.bytes = 4.0 * batch * (double(Rj / 2) * (Cj / 2) + double(Rj) * Cj + double(a.out_h) * a.out_w);
+        const double c_b = (j == g.J && fq) ? 2.0 : 4.0;
+        const double ch_b = (l == 2 && fq) ? 2.0 : 4.0;
+        d.bytes = batch * (c_b * double(Rj / 2) * (Cj / 2) + ch_b * double(Rj) * Cj +
+                           4.0 * double(a.out_h) * a.out_w);
         push(d);
     }
 }
@@ -467,6 +505,8 @@ int fill_quant_args(const Geometry& g, QuantArgs* a) {
     a->sub_off[g.nsub] = int(g.ncoef);
     a->nsub = g.nsub;
     a->ncoef = g.ncoef;
+    a->nq = g.ncoef;
+    a->in_plane = g.ncoef;
     a->low_n = g.low_n;
     int64_t parts = (g.low_n + 4095) / 4096;
     if (parts < 1) parts = 1;
@@ -499,6 +539,35 @@ int build_quant_chain(const Geometry& g, int batch, const float* coeffs, const f
     d.type = kStQuantize;
     d.ntiles = int((g.ncoef + 4095) / 4096) * batch;
     d.bytes = 6.0 * batch * double(g.ncoef);
+    chain.push_back(d);
+    return CT_OK;
+}
+
+int build_lowpass_quant_chain(const Geometry& g, int batch, const float* low, int64_t low_plane,
+                              const float* steps, int steps_stride, int16_t* idx, float* side,
+                              char* ws, const Workspace& w, std::vector<StageDesc>& chain) {
+    StageDesc d;
+    memset(&d, 0, sizeof(d));
+    int rc = fill_quant_args(g, &d.u.q);
+    if (rc != CT_OK) return rc;
+    QuantArgs& a = d.u.q;
+    a.coeffs = low;
+    a.in_plane = low_plane;
+    a.nq = g.low_n;
+    a.idx = idx;
+    a.side = side;
+    a.steps = steps;
+    a.steps_stride = steps_stride;
+    a.partials = reinterpret_cast<float*>(ws + w.part_off);
+    a.vec8 = g.ncoef % 8 == 0 && low_plane % 8 == 0 && g.low_n % 8 == 0 && aligned16(low) && aligned16(idx);
+    d.batch = batch;
+    d.type = kStPartial;
+    d.ntiles = a.nparts * batch;
+    d.bytes = 4.0 * batch * double(g.low_n);
+    chain.push_back(d);
+    d.type = kStQuantize;
+    d.ntiles = int((g.low_n + 4095) / 4096) * batch;
+    d.bytes = 6.0 * batch * double(g.low_n);
     chain.push_back(d);
     return CT_OK;
 }
@@ -605,6 +674,50 @@ int ct_dequantize(const ct_geom* geom, int32_t batch, const int16_t* idx, const 
     std::vector<StageDesc> chain;
     rc = build_dequant_chain(g, batch, idx, steps, steps_stride, side, coeffs, chain);
     if (rc != CT_OK) return rc;
+    return launch_chain(chain, stream);
+}
+
+int ct_encode(const ct_geom* geom, int32_t batch, const float* planes, const float* steps,
+              int32_t steps_stride, int16_t* idx, float* side, float* coeffs, void* ws,
+              size_t ws_bytes, hipStream_t stream) {
+    Geometry g;
+    int rc = check_common(geom, batch, &g);
+    if (rc != CT_OK) return rc;
+    if (batch == 0) return CT_OK;
+    if (!planes || !steps || !idx || !side || !ws) return CT_ERR_ARG;
+    if (steps_stride < 0 || (steps_stride > 0 && steps_stride < g.nsub)) return CT_ERR_ARG;
+    const Workspace w = workspace_layout(g, batch);
+    if (ws_bytes < w.total) return CT_ERR_WORKSPACE;
+    if (!constants().ok) return CT_ERR_UNSUPPORTED;
+    if (fault_injected()) return CT_ERR_HIP;
+    char* wsc = static_cast<char*>(ws);
+    const FusedQuant fq{idx, steps, steps_stride, nullptr};
+    std::vector<StageDesc> chain;
+    build_transform_chain(g, batch, kModeForward, planes, coeffs, wsc, w, kDefaultGrouping, chain, &fq);
+    const float* low = coeffs ? coeffs : reinterpret_cast<const float*>(wsc + w.low_off);
+    rc = build_lowpass_quant_chain(g, batch, low, coeffs ? g.ncoef : g.low_n, steps, steps_stride, idx,
+                                   side, wsc, w, chain);
+    if (rc != CT_OK) return rc;
+    return launch_chain(chain, stream);
+}
+
+int ct_decode(const ct_geom* geom, int32_t batch, const int16_t* idx, const float* steps,
+              int32_t steps_stride, const float* side, float* planes, void* ws, size_t ws_bytes,
+              hipStream_t stream) {
+    Geometry g;
+    int rc = check_common(geom, batch, &g);
+    if (rc != CT_OK) return rc;
+    if (batch == 0) return CT_OK;
+    if (!idx || !steps || !side || !planes || !ws) return CT_ERR_ARG;
+    if (steps_stride < 0 || (steps_stride > 0 && steps_stride < g.nsub)) return CT_ERR_ARG;
+    const Workspace w = workspace_layout(g, batch);
+    if (ws_bytes < w.total) return CT_ERR_WORKSPACE;
+    if (!constants().ok) return CT_ERR_UNSUPPORTED;
+    if (fault_injected()) return CT_ERR_HIP;
+    const FusedQuant fq{const_cast<int16_t*>(idx), steps, steps_stride, side};
+    std::vector<StageDesc> chain;
+    build_transform_chain(g, batch, kModeInverse, nullptr, planes, static_cast<char*>(ws), w,
+                          kDefaultGrouping, chain, &fq);
     return launch_chain(chain, stream);
 }
 

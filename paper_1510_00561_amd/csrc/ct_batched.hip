@@ -1,5 +1,8 @@
 // Group kernels of the batched form (gfx950).
 //
+// Plans run the separate forward, quantise, dequantise and inverse stages, so
+// the group kernels use the stage variants without quantised I/O.
+//
 // One launch runs the stages of one type at one chain position of every
 // stream of a plan: a workgroup finds its stage among the group's stages by
 // binary search over their first tiles and runs that tile with the same
@@ -49,22 +52,22 @@ __global__ __launch_bounds__(NT) void group_kernel(const StageDesc* stages, cons
     const StageDesc& d = stages[s];
     if constexpr (TYPE == kStLevelAna) {
         LA st(d.u.la);
-        st.run_tile(tile, smem);
+        st.template run_tile<false>(tile, smem);
     } else if constexpr (TYPE == kStLevelSyn) {
         LS st(d.u.ls);
-        st.run_tile(tile, smem);
+        st.template run_tile<false>(tile, smem);
     } else if constexpr (TYPE == kStSplit1Ana) {
         S1A st(d.u.sp, d.batch, d.lift);
-        st.run_tile(tile);
+        st.template run_tile<false>(tile);
     } else if constexpr (TYPE == kStSplit2Ana) {
         S2A st(d.u.sp, d.batch, d.lift);
-        st.run_tile(tile);
+        st.template run_tile<false>(tile);
     } else if constexpr (TYPE == kStSplit1Syn) {
         S1S st(d.u.sp, d.batch, d.lift);
-        st.run_tile(tile);
+        st.template run_tile<false>(tile);
     } else if constexpr (TYPE == kStSplit2Syn) {
         S2S st(d.u.sp, d.batch, d.lift);
-        st.run_tile(tile);
+        st.template run_tile<false>(tile);
     } else if constexpr (TYPE == kStPartial) {
         qstage::lowpass_partial<NT>(d.u.q, tile, smem);
     } else if constexpr (TYPE == kStQuantize) {

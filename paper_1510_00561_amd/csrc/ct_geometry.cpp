@@ -179,6 +179,8 @@ Workspace workspace_layout(const Geometry& g, int batch) {
     off = align256(off + B * plane);
     w.part_off = off;
     off = align256(off + B * kMaxPart * 2 * sizeof(float));
+    w.low_off = off;
+    off = align256(off + B * size_t(g.low_n) * sizeof(float));
     w.total = off;
     return w;
 }

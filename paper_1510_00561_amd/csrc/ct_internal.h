@@ -44,6 +44,7 @@ struct Workspace {
     size_t a_off = 0;                      // [B][R][C]
     size_t b_off = 0;                      // [B][R][C]
     size_t part_off = 0;                   // quantiser partials [B][kMaxPart][2]
+    size_t low_off = 0;                    // lowpass for the fused encoder [B][low_n]
     size_t total = 0;
 };
 constexpr int kMaxPart = 256;

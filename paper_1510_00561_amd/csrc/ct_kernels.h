@@ -55,6 +55,20 @@ struct Quad {
     float scale[4];
 };
 
+// Quantiser indices of the final subbands of one LP level, written by the
+// stage that produces them (encoder) or read by the stage that consumes them
+// (decoder), in the coefficient layout: element e of subband s of plane b is
+// idx[b * plane + e] with step steps[b * steps_stride + s]. The arithmetic is
+// that of ct_quantize / ct_dequantize on the float value the stage stores or
+// loads, so the fused paths give identical results.
+struct QuantIO {
+    int16_t* idx;            // null: the stage reads / writes float coefficients
+    int64_t plane;
+    const float* steps;
+    int steps_stride;
+    int sub0;                // subband index of the level's channel position 0
+};
+
 // One DFB tree level t >= 3 for all channels of an LP level whose image is
 // R_j x C_j. Channels of a tree level are stored back to back in subband
 // order; horizontal channels as (R_j / 2^(t-1)) x (C_j / 2), vertical ones
@@ -69,6 +83,7 @@ struct SplitArgs {
     float scale[64];    // per child channel (applied on store / load)
     int use_scale;
     int bh;             // rows per streamed block (multiple of 4), see block_rows()
+    QuantIO q;          // final subbands as indices (analysis: written; synthesis: read)
 };
 
 // Rows per streamed block of a register-streaming stage. A wavefront streams
@@ -151,7 +166,9 @@ struct QuantArgs {
     const float* steps;
     int steps_stride;
     float* partials;         // [batch][kMaxPart][2]
-    int64_t ncoef;
+    int64_t ncoef;           // coefficients per plane; plane stride of idx (and of coeffs_out)
+    int64_t nq;              // elements [0, nq) of each plane are quantised (ncoef, or low_n)
+    int64_t in_plane;        // plane stride of `coeffs` (ncoef, or low_n for a lowpass buffer)
     int64_t low_n;
     int nsub;
     int nparts;              // partial blocks per plane for the lowpass

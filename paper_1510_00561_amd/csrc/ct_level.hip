@@ -17,27 +17,27 @@ namespace {
 constexpr int NT_STREAM = 256;
 
 // One wavefront per (plane, column strip, row block).
-template <int LO_R, int UP_R>
+template <int LO_R, int UP_R, bool Q>
 __global__ __launch_bounds__(NT_STREAM) void stream_level_analysis_kernel(stage::LevelAnaArgs a) {
     using S = stream::StreamLevelAna<LO_R, UP_R, NT_STREAM>;
     __shared__ float smem[S::SMEM];
     S st(a);
-    st.run_tile(xcd_remap(blockIdx.x, gridDim.x), smem);
+    st.template run_tile<Q>(xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
-template <int LO_R, int UP_R>
+template <int LO_R, int UP_R, bool Q>
 __global__ __launch_bounds__(NT_STREAM) void stream_level_synthesis_kernel(stage::LevelSynArgs a) {
     using S = stream::StreamLevelSyn<LO_R, UP_R, NT_STREAM>;
     __shared__ float smem[S::SMEM];
     S st(a);
-    st.run_tile(xcd_remap(blockIdx.x, gridDim.x), smem);
+    st.template run_tile<Q>(xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
 // One wavefront per (plane, parent channel, column strip, row block).
-template <int LEVELS, bool ANA>
+template <int LEVELS, bool ANA, bool Q>
 __global__ __launch_bounds__(NT_STREAM) void stream_split_kernel(SplitArgs a, Lift L, int batch) {
     stream::StreamSplit<LEVELS, ANA, NT_STREAM> st(a, batch, L);
-    st.run_tile(xcd_remap(blockIdx.x, gridDim.x));
+    st.template run_tile<Q>(xcd_remap(blockIdx.x, gridDim.x));
 }
 
 __global__ __launch_bounds__(256) void pad_fold_kernel(CView in, int R, int C, View out, int H,
@@ -63,9 +63,11 @@ hipError_t launch_level_analysis(const stage::LevelAnaArgs& a, int lo_r, hipStre
     if (a.bh <= 0 || (a.bh & 7)) return hipErrorInvalidValue;
     constexpr int waves = NT_STREAM / 64;
     const int tiles = (level_items(a.R, a.C, a.batch, a.bh) + waves - 1) / waves;
-    if (lo_r == 4) stream_level_analysis_kernel<4, 3><<<tiles, NT_STREAM, 0, st>>>(a);
-    else if (lo_r == 3) stream_level_analysis_kernel<3, 4><<<tiles, NT_STREAM, 0, st>>>(a);
-    else return hipErrorInvalidValue;
+    const bool q = a.q.idx != nullptr;
+    if (lo_r == 4 && !q) stream_level_analysis_kernel<4, 3, false><<<tiles, NT_STREAM, 0, st>>>(a);
+    else if (lo_r == 4) stream_level_analysis_kernel<4, 3, true><<<tiles, NT_STREAM, 0, st>>>(a);
+    else if (lo_r == 3 && !q) stream_level_analysis_kernel<3, 4, false><<<tiles, NT_STREAM, 0, st>>>(a);
+    else return hipErrorInvalidValue;   // the transposes never quantise
     return hipGetLastError();
 }
 
@@ -73,8 +75,10 @@ hipError_t launch_level_synthesis(const stage::LevelSynArgs& a, int lo_r, hipStr
     if (a.bh <= 0 || (a.bh & 7)) return hipErrorInvalidValue;
     constexpr int waves = NT_STREAM / 64;
     const int tiles = (level_items(a.R, a.C, a.batch, a.bh) + waves - 1) / waves;
-    if (lo_r == 4) stream_level_synthesis_kernel<4, 3><<<tiles, NT_STREAM, 0, st>>>(a);
-    else if (lo_r == 3) stream_level_synthesis_kernel<3, 4><<<tiles, NT_STREAM, 0, st>>>(a);
+    const bool q = a.q.idx != nullptr || a.lq.idx != nullptr;
+    if (lo_r == 4 && !q) stream_level_synthesis_kernel<4, 3, false><<<tiles, NT_STREAM, 0, st>>>(a);
+    else if (lo_r == 4) stream_level_synthesis_kernel<4, 3, true><<<tiles, NT_STREAM, 0, st>>>(a);
+    else if (lo_r == 3 && !q) stream_level_synthesis_kernel<3, 4, false><<<tiles, NT_STREAM, 0, st>>>(a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -84,7 +88,8 @@ static hipError_t launch_split(const SplitArgs& a, Lift lift, int batch, hipStre
     if (a.bh <= 0 || (a.bh & 3)) return hipErrorInvalidValue;
     constexpr int waves = NT_STREAM / 64;
     const int tiles = (stream_items(a, batch, LEVELS) + waves - 1) / waves;
-    stream_split_kernel<LEVELS, ANA><<<tiles, NT_STREAM, 0, st>>>(a, lift, batch);
+    if (a.q.idx) stream_split_kernel<LEVELS, ANA, true><<<tiles, NT_STREAM, 0, st>>>(a, lift, batch);
+    else stream_split_kernel<LEVELS, ANA, false><<<tiles, NT_STREAM, 0, st>>>(a, lift, batch);
     return hipGetLastError();
 }
 

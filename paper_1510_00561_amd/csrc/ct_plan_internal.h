@@ -30,9 +30,22 @@ struct ProfScope {
 // Transform modes, in the order used by build_transform_chain.
 enum ChainMode { kModeForward = 0, kModeInverse = 1, kModeForwardAdjoint = 2, kModeInverseAdjoint = 3 };
 
+// Quantiser of the fused encoder / decoder: indices [B][ncoef] and steps as
+// for ct_quantize; `side` is read by the decoder.
+struct FusedQuant {
+    int16_t* idx;
+    const float* steps;
+    int steps_stride;
+    const float* side;
+};
 void build_transform_chain(const Geometry& g, int batch, int mode, const float* in, float* out,
                            char* ws, const Workspace& w, const int* grouping,
-                           std::vector<StageDesc>& chain);
+                           std::vector<StageDesc>& chain, const FusedQuant* fq = nullptr);
+// Quantiser stages of the lowpass alone (fused encoder): `low` holds each
+// plane's lowpass at stride `low_plane`.
+int build_lowpass_quant_chain(const Geometry& g, int batch, const float* low, int64_t low_plane,
+                              const float* steps, int steps_stride, int16_t* idx, float* side,
+                              char* ws, const Workspace& w, std::vector<StageDesc>& chain);
 int build_quant_chain(const Geometry& g, int batch, const float* coeffs, const float* steps,
                       int steps_stride, int16_t* idx, float* side, char* ws, const Workspace& w,
                       std::vector<StageDesc>& chain);

@@ -30,8 +30,8 @@ __global__ __launch_bounds__(NT) void dequantize_kernel(QuantArgs A) {
     qstage::dequantize<NT>(A, blockIdx.x);
 }
 
-unsigned chunks(const QuantArgs& a, int batch) {
-    return unsigned((a.ncoef + qstage::CHUNK - 1) / qstage::CHUNK) * unsigned(batch);
+unsigned chunks(int64_t n, int batch) {
+    return unsigned((n + qstage::CHUNK - 1) / qstage::CHUNK) * unsigned(batch);
 }
 
 }  // namespace
@@ -42,12 +42,12 @@ hipError_t launch_lowpass_partial(const QuantArgs& a, int batch, hipStream_t st)
 }
 
 hipError_t launch_quantize(const QuantArgs& a, int batch, hipStream_t st) {
-    quantize_kernel<<<dim3(chunks(a, batch)), NT, 0, st>>>(a);
+    quantize_kernel<<<dim3(chunks(a.nq, batch)), NT, 0, st>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_dequantize(const QuantArgs& a, int batch, hipStream_t st) {
-    dequantize_kernel<<<dim3(chunks(a, batch)), NT, 0, st>>>(a);
+    dequantize_kernel<<<dim3(chunks(a.ncoef, batch)), NT, 0, st>>>(a);
     return hipGetLastError();
 }
 

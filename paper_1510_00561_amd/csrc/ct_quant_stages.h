@@ -59,7 +59,7 @@ __device__ __forceinline__ int find_subband(const QuantArgs& A, int64_t e) {
 
 __device__ __forceinline__ int partial_tiles(const QuantArgs& A, int batch) { return A.nparts * batch; }
 __device__ __forceinline__ int chunk_tiles(const QuantArgs& A, int batch) {
-    return int((A.ncoef + CHUNK - 1) / CHUNK) * batch;
+    return int((A.nq + CHUNK - 1) / CHUNK) * batch;
 }
 
 // Pass 1: (min, max) of one block of one plane's lowpass.
@@ -70,7 +70,7 @@ __device__ void lowpass_partial(const QuantArgs& A, int tile, float* red) {
     const int64_t per = (A.low_n + A.nparts - 1) / A.nparts;
     const int64_t lo = p * per;
     const int64_t hi = lo + per < A.low_n ? lo + per : A.low_n;
-    const float* c = A.coeffs + b * A.ncoef;
+    const float* c = A.coeffs + b * A.in_plane;
     float mn = INFINITY, mx = -INFINITY;
     for (int64_t e = lo + threadIdx.x; e < hi; e += NT) {
         const float v = c[e];
@@ -89,7 +89,7 @@ template <int NT>
 __device__ void quantize(const QuantArgs& A, int tile, float* red) {
 #pragma clang fp contract(off)
     constexpr int ITEMS = CHUNK / NT;
-    const int nch = int((A.ncoef + CHUNK - 1) / CHUNK);
+    const int nch = int((A.nq + CHUNK - 1) / CHUNK);
     const int b = tile / nch;
     const int64_t e0 = int64_t(tile - b * nch) * CHUNK;
     float mn = 0.f, mx = 0.f, sc = 0.f;
@@ -108,10 +108,10 @@ __device__ void quantize(const QuantArgs& A, int tile, float* red) {
             A.side[2 * b + 1] = mx;
         }
     }
-    const float* c = A.coeffs + b * A.ncoef;
+    const float* c = A.coeffs + b * A.in_plane;
     int16_t* q = A.idx + b * A.ncoef;
     const float* steps = A.steps + int64_t(b) * A.steps_stride;
-    const int64_t e_end = e0 + CHUNK < A.ncoef ? e0 + CHUNK : A.ncoef;
+    const int64_t e_end = e0 + CHUNK < A.nq ? e0 + CHUNK : A.nq;
     const int s0 = find_subband(A, e0);
     if (A.vec8 && A.sub_off[s0 + 1] >= e_end) {
         // the whole chunk lies in one subband: 8 consecutive coefficients per
@@ -151,12 +151,12 @@ __device__ void quantize(const QuantArgs& A, int tile, float* red) {
         return;
     }
     const int64_t e_first = e0 + threadIdx.x;
-    if (e_first >= A.ncoef) return;
+    if (e_first >= A.nq) return;
     float xs[ITEMS];
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
         const int64_t e = e_first + int64_t(it) * NT;
-        xs[it] = e < A.ncoef ? c[e] : 0.f;
+        xs[it] = e < A.nq ? c[e] : 0.f;
     }
     int s = find_subband(A, e_first);
     int64_t next = A.sub_off[s + 1];
@@ -164,7 +164,7 @@ __device__ void quantize(const QuantArgs& A, int tile, float* red) {
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
         const int64_t e = e_first + int64_t(it) * NT;
-        if (e >= A.ncoef) break;
+        if (e >= A.nq) break;
         while (e >= next) {
             ++s;
             next = A.sub_off[s + 1];

@@ -21,6 +21,7 @@ struct LevelAnaArgs {
     Lift L;
     int batch;
     int bh;                 // rows per streamed block, a multiple of 8
+    QuantIO q;              // the four channels as indices (levels with 4 directions)
 };
 
 // DFB tree levels 1-2 + LP level, synthesis: the four channels `in` and the
@@ -35,6 +36,9 @@ struct LevelSynArgs {
     Lift L;
     int batch;
     int bh;                 // rows per streamed block, a multiple of 8
+    QuantIO q;              // the four channels as indices (levels with 4 directions)
+    QuantIO lq;             // the lowpass c_in as indices (coarsest level)
+    const float* side;      // [batch][2] lowpass (min, max), with lq
 };
 
 // Geometry of a parent channel at tree level t-1 (split at level t).

@@ -26,6 +26,7 @@
 // strip are loaded but not stored.
 #pragma once
 
+#include "ct_quant_stages.h"
 #include "ct_stages.h"
 
 #include <math.h>
@@ -101,19 +102,20 @@ struct StreamSplit {
     }
     static constexpr int slot(int rel) { return ((rel % RING) + RING) % RING; }
 
-    __device__ void run_tile(int tile) const {
+    // QUANT must match A.q.idx != nullptr (the launcher picks the kernel).
+    template <bool QUANT>
+    __device__ __forceinline__ void run_tile(int tile) const {
         const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
         const int item = tile * WAVES + wave;
-        if (item < items()) run_item(item);
+        if (item >= items()) return;
+        if (lift.first_odd) run<1, QUANT>(item);
+        else run<0, QUANT>(item);
     }
 
-    __device__ void run_item(int item) const {
-        if (lift.first_odd) run<1>(item);
-        else run<0>(item);
-    }
-
-    template <int FO>
-    __device__ void run(int item) const {
+    // QUANT: the final subbands are indices (analysis: quantised on store,
+    // synthesis: dequantised on load) with the quantiser's arithmetic.
+    template <int FO, bool QUANT>
+    __device__ __forceinline__ void run(int item) const {
         const StreamCounts cnt = stream_counts(A, LEVELS);
         const int nh = cnt.nh, ih = cnt.ih, iv = cnt.iv, sh = cnt.sh, sv = cnt.sv;
         const int per_plane = nh * (ih + iv);
@@ -151,8 +153,10 @@ struct StreamSplit {
         const int a4b = 4 * pmod(4 * g.a, nc);      // column-base drift per superstep (bytes)
         const int r4 = 4 % nr;                      // row advance per superstep modulo nr
 
-        const float* src = A.parent + b * A.parent_plane;
-        float* dst = A.child + b * A.child_plane;
+        const float* src = A.parent ? A.parent + b * A.parent_plane : nullptr;
+        float* dst = A.child ? A.child + b * A.child_plane : nullptr;
+        int16_t* qplane = QUANT ? A.q.idx + b * A.q.plane : nullptr;
+        const float* qsteps = QUANT ? A.q.steps + int64_t(b) * A.q.steps_stride : nullptr;
         const int64_t cs1 = A.plane_elems >> t;          // child channel size (one level)
         const int64_t cs2 = A.plane_elems >> (t + 1);    // grandchild channel size
 
@@ -163,6 +167,8 @@ struct StreamSplit {
         const float* lbase[4];
         float* sbase[4];
         float lsc[4], ssc[4];
+        int16_t* qbase[4];        // QUANT: indices of the final subband of row class r
+        float qstep[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             lrow[r] = pmod(S + r, nr);
@@ -176,15 +182,18 @@ struct StreamSplit {
             if (ANA) {
                 lbase[r] = src + g.parent_off;
                 lsc[r] = 1.f;
-                sbase[r] = dst + pos * cs;
+                sbase[r] = dst ? dst + pos * cs : nullptr;
                 ssc[r] = sc;
             } else {
-                lbase[r] = src + pos * cs;
+                lbase[r] = src ? src + pos * cs : nullptr;
                 lsc[r] = sc;
                 sbase[r] = dst + g.parent_off;
                 ssc[r] = 1.f;
             }
+            qbase[r] = QUANT ? qplane + pos * cs : nullptr;
+            qstep[r] = QUANT ? qsteps[A.q.sub0 + pos] : 1.f;
         }
+        const bool store_float = !ANA || !QUANT || dst != nullptr;
         // rows of the arrays that hold the superstep's rows: parents are
         // addressed by the row itself, children by row >> 1, grandchildren
         // by row >> 2
@@ -199,13 +208,22 @@ struct StreamSplit {
         auto load4 = [&](int u_next) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const char* rp = reinterpret_cast<const char*>(lbase[r] + int64_t(lrow[r] >> LSH) * nc);
+                const char* rp = (!ANA && QUANT) ? nullptr
+                                 : reinterpret_cast<const char*>(lbase[r] + int64_t(lrow[r] >> LSH) * nc);
                 uint32_t o0 = uint32_t(lcb[r]) + m0, o1 = uint32_t(lcb[r]) + m1;
                 o0 = min(o0, o0 - ncb);
                 o1 = min(o1, o1 - ncb);
                 Pair& X = w[slot(4 * u_next + r)];
-                X.x = lsc[r] * *reinterpret_cast<const float*>(rp + o0);
-                X.y = lsc[r] * *reinterpret_cast<const float*>(rp + o1);
+                if (!ANA && QUANT) {
+                    // dequantise on load: (q * step) * scale, as ct_dequantize
+                    // followed by a float load would compute
+                    const int16_t* qr = qbase[r] + int64_t(lrow[r] >> LSH) * nc;
+                    X.x = lsc[r] * __fmul_rn(float(qr[o0 >> 2]), qstep[r]);
+                    X.y = lsc[r] * __fmul_rn(float(qr[o1 >> 2]), qstep[r]);
+                } else {
+                    X.x = lsc[r] * *reinterpret_cast<const float*>(rp + o0);
+                    X.y = lsc[r] * *reinterpret_cast<const float*>(rp + o1);
+                }
                 lrow[r] += r4;
                 lrow[r] = lrow[r] >= nr ? lrow[r] - nr : lrow[r];
                 lcb[r] -= a4b;
@@ -222,10 +240,20 @@ struct StreamSplit {
                 scb[r] -= a4b;
                 scb[r] = scb[r] < 0 ? scb[r] + int(ncb) : scb[r];
                 if (i < rb || i >= re) continue;
-                char* rp = reinterpret_cast<char*>(sbase[r] + int64_t(i >> SSH) * nc);
                 const Pair& X = w[slot(4 * u - TL + r)];
-                if (st0) *reinterpret_cast<float*>(rp + o0) = ssc[r] * X.x;
-                if (st1) *reinterpret_cast<float*>(rp + o1) = ssc[r] * X.y;
+                const float v0 = ssc[r] * X.x, v1 = ssc[r] * X.y;
+                if (store_float) {
+                    char* rp = reinterpret_cast<char*>(sbase[r] + int64_t(i >> SSH) * nc);
+                    if (st0) *reinterpret_cast<float*>(rp + o0) = v0;
+                    if (st1) *reinterpret_cast<float*>(rp + o1) = v1;
+                }
+                if (ANA && QUANT) {
+                    // quantise on store: round(c / step), as ct_quantize on the
+                    // stored float
+                    int16_t* qr = qbase[r] + int64_t(i >> SSH) * nc;
+                    if (st0) qr[o0 >> 2] = qstage::to_index(__fdiv_rn(v0, qstep[r]));
+                    if (st1) qr[o1 >> 2] = qstage::to_index(__fdiv_rn(v1, qstep[r]));
+                }
             }
         };
 

@@ -25,6 +25,7 @@
 // side of the 96 columns they store.
 #pragma once
 
+#include "ct_quant_stages.h"
 #include "ct_stream.h"
 
 namespace ct {
@@ -96,18 +97,21 @@ struct StreamLevelAna {
     static constexpr int rslot(int rel) { return ((rel % RR) + RR) % RR; }
     static constexpr int cslot(int rel) { return ((rel % RC) + RC) % RC; }
 
-    __device__ void run_tile(int tile, float* smem) const {
+    // QOUT must match A.q.idx != nullptr (the launcher picks the kernel).
+    template <bool QOUT>
+    __device__ __forceinline__ void run_tile(int tile, float* smem) const {
         const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
         const int item = tile * WAVES + wave;
         if (item < items()) {
             float* T = smem + wave * WAVE_SMEM;
-            if (A.L.first_odd) run<1>(item, T);
-            else run<0>(item, T);
+            if (A.L.first_odd) run<1, QOUT>(item, T);
+            else run<0, QOUT>(item, T);
         }
     }
 
-    template <int FO>
-    __device__ void run(int item, float* T) const {
+    // QOUT: the four channels are final subbands quantised on store
+    template <int FO, bool QOUT>
+    __device__ __forceinline__ void run(int item, float* T) const {
         const int ns = strips(), nb = blocks();
         const int b = item / (ns * nb);
         const int rem = item - b * ns * nb;
@@ -155,12 +159,21 @@ struct StreamLevelAna {
         };
 
         float* cp = A.c_out.p + b * A.c_out.plane;
-        float* q0 = A.out.p[0] + b * A.out.plane;
-        float* q1 = A.out.p[1] + b * A.out.plane;
-        float* q2 = A.out.p[2] + b * A.out.plane;
-        float* q3 = A.out.p[3] + b * A.out.plane;
+        // the four channels as floats (out.p[0] null: not written) and, for a
+        // level with four directions under the encoder, as indices
+        const bool fout = A.out.p[0] != nullptr;
+        float* q0 = fout ? A.out.p[0] + b * A.out.plane : nullptr;
+        float* q1 = fout ? A.out.p[1] + b * A.out.plane : nullptr;
+        float* q2 = fout ? A.out.p[2] + b * A.out.plane : nullptr;
+        float* q3 = fout ? A.out.p[3] + b * A.out.plane : nullptr;
         const float s0 = A.out.scale[0], s1 = A.out.scale[1];
         const float s2 = A.out.scale[2], s3 = A.out.scale[3];
+        constexpr bool qout = QOUT;
+        const int64_t q4 = int64_t(Rh) * Ch;
+        int16_t* x0 = qout ? A.q.idx + b * A.q.plane : nullptr;
+        const float* qst = qout ? A.q.steps + int64_t(b) * A.q.steps_stride + A.q.sub0 : nullptr;
+        const float d0 = qout ? qst[0] : 1.f, d1 = qout ? qst[1] : 1.f;
+        const float d2 = qout ? qst[2] : 1.f, d3 = qout ? qst[3] : 1.f;
 
         // transposed flush of `cnt` compact rows starting at compact row i0:
         // four compact columns per instruction, VB rows each
@@ -175,8 +188,15 @@ struct StreamLevelAna {
                 const int k = (cb0 >> 1) + l;
                 if (li < cnt && k < Ch) {
                     const int64_t o = int64_t(k) * Rh + i0 + li;
-                    q2[o] = T[l * VLD + li];
-                    q3[o] = T[(64 + l) * VLD + li];
+                    const float a = T[l * VLD + li], e = T[(64 + l) * VLD + li];
+                    if (fout) {
+                        q2[o] = a;
+                        q3[o] = e;
+                    }
+                    if (qout) {
+                        x0[2 * q4 + o] = qstage::to_index(__fdiv_rn(a, d2));
+                        x0[3 * q4 + o] = qstage::to_index(__fdiv_rn(e, d3));
+                    }
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -274,8 +294,16 @@ struct StreamLevelAna {
                     if (i >= (rb >> 1) && i < (re >> 1)) {
                         const Pair E = dr[rslot(2 * u - 16)], O = dr[rslot(2 * u - 15)];
                         if (own) {
-                            q0[int64_t(i) * Ch + kc] = s0 * E.y;
-                            q1[int64_t(i) * Ch + kc] = s1 * O.x;
+                            const float a = s0 * E.y, e = s1 * O.x;
+                            const int64_t o = int64_t(i) * Ch + kc;
+                            if (fout) {
+                                q0[o] = a;
+                                q1[o] = e;
+                            }
+                            if (qout) {
+                                x0[o] = qstage::to_index(__fdiv_rn(a, d0));
+                                x0[q4 + o] = qstage::to_index(__fdiv_rn(e, d1));
+                            }
                         }
                         const int slot = (i - (rb >> 1)) & (VB - 1);
                         T[lane * VLD + slot] = s2 * E.x;
@@ -339,18 +367,21 @@ struct StreamLevelSyn {
     static constexpr int hslot(int rel) { return ((rel % RH) + RH) % RH; }
     static constexpr int cslot(int rel) { return ((rel % RC) + RC) % RC; }
 
-    __device__ void run_tile(int tile, float* smem) const {
+    // QIN must match (A.q.idx or A.lq.idx) != nullptr (the launcher picks the kernel).
+    template <bool QIN>
+    __device__ __forceinline__ void run_tile(int tile, float* smem) const {
         const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
         const int item = tile * WAVES + wave;
         if (item < items()) {
             float* T = smem + wave * WAVE_SMEM;
-            if (A.L.first_odd) run<1>(item, T);
-            else run<0>(item, T);
+            if (A.L.first_odd) run<1, QIN>(item, T);
+            else run<0, QIN>(item, T);
         }
     }
 
-    template <int FO>
-    __device__ void run(int item, float* T) const {
+    // QIN: the four channels and / or the lowpass are indices dequantised on load
+    template <int FO, bool QIN>
+    __device__ __forceinline__ void run(int item, float* T) const {
         const int ns = strips(), nb = blocks();
         const int b = item / (ns * nb);
         const int rem = item - b * ns * nb;
@@ -368,13 +399,31 @@ struct StreamLevelSyn {
         const int j0 = cb0 + 2 * lane;                   // image columns j0, j0 + 1
         const bool st0 = own && j0 < ow, st1 = own && j0 + 1 < ow;
 
-        const float* h0 = A.in.p[0] + b * A.in.plane;    // H a=-1: even rows, odd columns
-        const float* h1 = A.in.p[1] + b * A.in.plane;    // H a=0:  odd rows, even columns
-        const float* v2 = A.in.p[2] + b * A.in.plane;    // V a=0:  even rows, even columns
-        const float* v3 = A.in.p[3] + b * A.in.plane;    // V a=-1: odd rows, odd columns
+        // the four channels as floats, or (decoder, levels with four
+        // directions) as indices dequantised on load
+        const bool qin = QIN && A.q.idx != nullptr;
+        const float* h0 = qin ? nullptr : A.in.p[0] + b * A.in.plane;   // H a=-1: even rows, odd columns
+        const float* h1 = qin ? nullptr : A.in.p[1] + b * A.in.plane;   // H a=0:  odd rows, even columns
+        const float* v2 = qin ? nullptr : A.in.p[2] + b * A.in.plane;   // V a=0:  even rows, even columns
+        const float* v3 = qin ? nullptr : A.in.p[3] + b * A.in.plane;   // V a=-1: odd rows, odd columns
         const float s0 = A.in.scale[0], s1 = A.in.scale[1];
         const float s2 = A.in.scale[2], s3 = A.in.scale[3];
-        const float* cin = A.c_in.p + b * A.c_in.plane;
+        const int64_t q4 = int64_t(Rh) * Ch;
+        const int16_t* x0 = qin ? A.q.idx + b * A.q.plane : nullptr;
+        const float* qst = qin ? A.q.steps + int64_t(b) * A.q.steps_stride + A.q.sub0 : nullptr;
+        const float d0 = qin ? qst[0] : 1.f, d1 = qin ? qst[1] : 1.f;
+        const float d2 = qin ? qst[2] : 1.f, d3 = qin ? qst[3] : 1.f;
+        // the lowpass c_in as floats, or (decoder, coarsest level) as indices
+        const bool lin = QIN && A.lq.idx != nullptr;
+        const float* cin = lin ? nullptr : A.c_in.p + b * A.c_in.plane;
+        const int16_t* lx = lin ? A.lq.idx + b * A.lq.plane : nullptr;
+        float l_mn = 0.f, l_step = 1.f, l_r = 0.f;
+        if (lin) {
+            l_mn = A.side[2 * b];
+            const float l_mx = A.side[2 * b + 1];
+            l_step = A.lq.steps[int64_t(b) * A.lq.steps_stride];
+            l_r = __fdiv_rn(__fsub_rn(l_mx, l_mn), 255.f);
+        }
         float* xo = A.x_out.p + b * A.x_out.plane;
 
         // Staging of the transposed channels, compact rows [i0, i0 + 16) of the
@@ -382,7 +431,7 @@ struct StreamLevelSyn {
         // of columns 16 c + cg, c = 0..3. Blocks aligned to 4 rows and inside
         // the array are read as one 16-byte load per column; wrapping or
         // unaligned blocks element by element.
-        const bool vec_ok = (Rh & 3) == 0 &&
+        const bool vec_ok = !qin && (Rh & 3) == 0 &&
                             ((reinterpret_cast<uintptr_t>(v2) | reinterpret_cast<uintptr_t>(v3)) & 15) == 0;
         const int cg = lane >> 2, rc = lane & 3;
         int64_t kcol[4];
@@ -411,8 +460,13 @@ struct StreamLevelSyn {
                     const int i = pmod(i0 + 4 * rc + e, Rh);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
-                        stg[4 * c + e] = v2[kcol[c] + i];
-                        stg[16 + 4 * c + e] = v3[kcol[c] + i];
+                        if (qin) {
+                            stg[4 * c + e] = __fmul_rn(float(x0[2 * q4 + kcol[c] + i]), d2);
+                            stg[16 + 4 * c + e] = __fmul_rn(float(x0[3 * q4 + kcol[c] + i]), d3);
+                        } else {
+                            stg[4 * c + e] = v2[kcol[c] + i];
+                            stg[16 + 4 * c + e] = v3[kcol[c] + i];
+                        }
                     }
                 }
             }
@@ -439,12 +493,24 @@ struct StreamLevelSyn {
         Pair hn;                            // prefetched H values of the next compact row
         float cn;                           // prefetched lowpass value
         auto load_h = [&]() {
-            hn.x = h1[int64_t(hrow) * Ch + kcw];   // odd row, even column
-            hn.y = h0[int64_t(hrow) * Ch + kcw];   // even row, odd column
+            const int64_t o = int64_t(hrow) * Ch + kcw;
+            if (qin) {
+                hn.x = __fmul_rn(float(x0[q4 + o]), d1);   // odd row, even column
+                hn.y = __fmul_rn(float(x0[o]), d0);        // even row, odd column
+            } else {
+                hn.x = h1[o];
+                hn.y = h0[o];
+            }
             hrow = hrow + 1 == Rh ? 0 : hrow + 1;
         };
         auto load_c = [&]() {
-            cn = cin[int64_t(crow) * A.c_in.ld + kcw];
+            if (lin) {
+                // the lowpass dequantised as ct_dequantize does
+                const float w = __fmul_rn(float(lx[int64_t(crow) * A.c_in.ld + kcw]), l_step);
+                cn = __fadd_rn(l_mn, __fmul_rn(w, l_r));
+            } else {
+                cn = cin[int64_t(crow) * A.c_in.ld + kcw];
+            }
             crow = crow + 1 == Rh ? 0 : crow + 1;
         };
 

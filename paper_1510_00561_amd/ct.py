@@ -94,6 +94,8 @@ def _lib():
             "ct_inverse_adjoint": [G, i32, P, P, P, sz, P],
             "ct_quantize": [G, i32, P, P, i32, P, P, P, sz, P],
             "ct_dequantize": [G, i32, P, P, i32, P, P, P],
+            "ct_encode": [G, i32, P, P, i32, P, P, P, P, sz, P],
+            "ct_decode": [G, i32, P, P, i32, P, P, P, sz, P],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -254,6 +256,45 @@ class Plan:
                                   ctypes.c_void_p(side.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                   self._stream())
         _check("ct_dequantize", rc)
+        return out
+
+    def encode(self, x, steps, idx=None, side=None, coeffs=None):
+        """Fused forward CT + quantise: (idx [B, ncoef] int16, side [B, 2]);
+        `coeffs` (optional [B, ncoef] float32) also receives the coefficients."""
+        B = self.batch
+        self._check_tensor(x, (B, self.height, self.width), torch.float32, "planes")
+        steps, stride = self._steps(steps)
+        if idx is None:
+            idx = torch.empty((B, self.ncoef), dtype=torch.int16, device=x.device)
+        if side is None:
+            side = torch.empty((B, 2), dtype=torch.float32, device=x.device)
+        self._check_tensor(idx, (B, self.ncoef), torch.int16, "idx")
+        self._check_tensor(side, (B, 2), torch.float32, "side")
+        cptr = None
+        if coeffs is not None:
+            self._check_tensor(coeffs, (B, self.ncoef), torch.float32, "coeffs")
+            cptr = coeffs.data_ptr()
+        rc = _lib().ct_encode(ctypes.byref(self.g), B, ctypes.c_void_p(x.data_ptr()),
+                              ctypes.c_void_p(steps.data_ptr()), stride, ctypes.c_void_p(idx.data_ptr()),
+                              ctypes.c_void_p(side.data_ptr()), ctypes.c_void_p(cptr),
+                              ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, self._stream())
+        _check("ct_encode", rc)
+        return idx, side
+
+    def decode(self, idx, steps, side, out=None):
+        """Fused dequantise + inverse CT: planes [B, H, W] float32."""
+        B = self.batch
+        self._check_tensor(idx, (B, self.ncoef), torch.int16, "idx")
+        self._check_tensor(side, (B, 2), torch.float32, "side")
+        steps, stride = self._steps(steps)
+        if out is None:
+            out = torch.empty((B, self.height, self.width), dtype=torch.float32, device=idx.device)
+        self._check_tensor(out, (B, self.height, self.width), torch.float32, "planes")
+        rc = _lib().ct_decode(ctypes.byref(self.g), B, ctypes.c_void_p(idx.data_ptr()),
+                              ctypes.c_void_p(steps.data_ptr()), stride, ctypes.c_void_p(side.data_ptr()),
+                              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                              self.ws_bytes, self._stream())
+        _check("ct_decode", rc)
         return out
 
 
