@@ -76,7 +76,9 @@ struct StreamSplit {
     static constexpr int TL = stream_halo(LEVELS);         // total lag = halo rows = halo columns
     static constexpr int HC = TL;
     static constexpr int VW = stream_cols(LEVELS);         // stored columns per strip
-    static constexpr int RING = LEVELS == 1 ? 16 : 24;     // ring rows (multiple of 4)
+    // ring rows (multiple of 4): the rows the steps still read, plus two
+    // supersteps of prefetched rows
+    static constexpr int RING = LEVELS == 1 ? 20 : 28;
     static constexpr int UNROLL = RING / 4;
     static constexpr int NSTEP = 4 * LEVELS;
 
@@ -258,12 +260,14 @@ struct StreamSplit {
         };
 
         load4(0);
+        load4(1);
         for (int n0 = 0; n0 < NS; n0 += UNROLL) {
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
-                // the next superstep's rows go into ring slots that no step
-                // of this superstep reads
-                load4(u + 1);
+                // the rows of the superstep after next go into ring slots that
+                // no step of this superstep reads (two supersteps of latency
+                // hiding)
+                load4(u + 2);
 #pragma unroll
                 for (int q = 0; q < NSTEP; ++q) apply_step<FO>(w, u, q);
                 store4(u, n0 + u);
