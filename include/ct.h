@@ -253,6 +253,8 @@ typedef struct ct_plan_info_t {
 
 #define CT_PLAN_GRAPH 1
 #define CT_PLAN_AUTOTUNE 2
+#define CT_PLAN_FUSED 4     /* fused encoder and decoder (as ct_encode, ct_decode): deq is not
+                               written and may be NULL, coeffs only when not NULL */
 
 int ct_plan_create(const ct_stream_desc* streams, int32_t n, int32_t flags, ct_plan** out);
 int ct_plan_run(ct_plan* plan, hipStream_t stream);

@@ -258,7 +258,10 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                 a.out.scale[k] = l == 2 ? sc[k] : 1.f;
             }
             a.out.plane = l == 2 ? g.ncoef : RC;
-            if (l == 2) a.q = qio;
+            if (l == 2 && qio.idx) {
+                a.q = qio;
+                d.type = kStLevelAnaQ;
+            }
             a.lo = lo;
             a.up = up;
             a.L = L;
@@ -293,6 +296,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     sa.use_scale = 1;
                     memcpy(sa.scale, sc, sizeof(float) * (1 << l));
                     sa.q = qio;
+                    if (qio.idx) e.type = count[gi] == 2 ? kStSplit2AnaQ : kStSplit1AnaQ;
                 } else {
                     sa.child = other;
                     sa.child_plane = RC;
@@ -331,6 +335,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
             }
             a.in.plane = g.ncoef;
             a.q = qio;
+            if (qio.idx) d.type = kStLevelSynQ;
         } else {
             int first[4], count[4];
             const int ng = split_groups(l, grouping[j - 1], first, count);
@@ -353,6 +358,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     sa.use_scale = 1;
                     memcpy(sa.scale, sc, sizeof(float) * (1 << l));
                     sa.q = qio;
+                    if (qio.idx) e.type = count[gi] == 2 ? kStSplit2SynQ : kStSplit1SynQ;
                 } else {
                     sa.parent = other;
                     sa.parent_plane = RC;
@@ -379,6 +385,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
             // fused decoder: the lowpass indices, dequantised on load
             a.lq = QuantIO{const_cast<int16_t*>(fq->idx), g.ncoef, fq->steps, fq->steps_stride, 0};
             a.side = fq->side;
+            d.type = kStLevelSynQ;
         }
         a.R = Rj;
         a.C = Cj;
@@ -413,27 +420,39 @@ namespace {
 
 const char* stage_name(int type) {
     switch (type) {
-        case kStLevelAna: return "lp_dfb12_analysis";
-        case kStSplit1Ana: return "dfb_split_analysis";
-        case kStSplit2Ana: return "dfb_split2_analysis";
+        case kStLevelAna:
+        case kStLevelAnaQ: return "lp_dfb12_analysis";
+        case kStSplit1Ana:
+        case kStSplit1AnaQ: return "dfb_split_analysis";
+        case kStSplit2Ana:
+        case kStSplit2AnaQ: return "dfb_split2_analysis";
         case kStPartial: return "lowpass_partial";
         case kStQuantize: return "quantize";
         case kStDequantize: return "dequantize";
-        case kStSplit1Syn: return "dfb_split_synthesis";
-        case kStSplit2Syn: return "dfb_split2_synthesis";
-        case kStLevelSyn: return "dfb12_lp_synthesis";
+        case kStSplit1Syn:
+        case kStSplit1SynQ: return "dfb_split_synthesis";
+        case kStSplit2Syn:
+        case kStSplit2SynQ: return "dfb_split2_synthesis";
+        case kStLevelSyn:
+        case kStLevelSynQ: return "dfb12_lp_synthesis";
         default: return "unknown";
     }
 }
 
 hipError_t launch_stage_raw(const StageDesc& d, hipStream_t st) {
     switch (d.type) {
-        case kStLevelAna: return launch_level_analysis(d.u.la, d.lo_r, st);
-        case kStLevelSyn: return launch_level_synthesis(d.u.ls, d.lo_r, st);
-        case kStSplit1Ana: return launch_dfb_split_analysis(d.u.sp, d.lift, d.batch, st);
-        case kStSplit2Ana: return launch_dfb_split2_analysis(d.u.sp, d.lift, d.batch, st);
-        case kStSplit1Syn: return launch_dfb_split_synthesis(d.u.sp, d.lift, d.batch, st);
-        case kStSplit2Syn: return launch_dfb_split2_synthesis(d.u.sp, d.lift, d.batch, st);
+        case kStLevelAna:
+        case kStLevelAnaQ: return launch_level_analysis(d.u.la, d.lo_r, st);
+        case kStLevelSyn:
+        case kStLevelSynQ: return launch_level_synthesis(d.u.ls, d.lo_r, st);
+        case kStSplit1Ana:
+        case kStSplit1AnaQ: return launch_dfb_split_analysis(d.u.sp, d.lift, d.batch, st);
+        case kStSplit2Ana:
+        case kStSplit2AnaQ: return launch_dfb_split2_analysis(d.u.sp, d.lift, d.batch, st);
+        case kStSplit1Syn:
+        case kStSplit1SynQ: return launch_dfb_split_synthesis(d.u.sp, d.lift, d.batch, st);
+        case kStSplit2Syn:
+        case kStSplit2SynQ: return launch_dfb_split2_synthesis(d.u.sp, d.lift, d.batch, st);
         case kStPartial: return launch_lowpass_partial(d.u.q, d.batch, st);
         case kStQuantize: return launch_quantize(d.u.q, d.batch, st);
         case kStDequantize: return launch_dequantize(d.u.q, d.batch, st);

@@ -25,7 +25,14 @@ enum StageType : int {
     kStSplit1Syn = 6,
     kStSplit2Syn = 7,
     kStLevelSyn = 8,     // DFB tree levels 1-2 + LP level, synthesis
-    kStNumTypes = 9,
+    // the same stages with quantised final subbands (fused encoder / decoder)
+    kStLevelAnaQ = 9,
+    kStSplit1AnaQ = 10,
+    kStSplit2AnaQ = 11,
+    kStSplit1SynQ = 12,
+    kStSplit2SynQ = 13,
+    kStLevelSynQ = 14,
+    kStNumTypes = 15,
 };
 
 struct StageDesc {

@@ -1,8 +1,5 @@
 // Group kernels of the batched form (gfx950).
 //
-// Plans run the separate forward, quantise, dequantise and inverse stages, so
-// the group kernels use the stage variants without quantised I/O.
-//
 // One launch runs the stages of one type at one chain position of every
 // stream of a plan: a workgroup finds its stage among the group's stages by
 // binary search over their first tiles and runs that tile with the same
@@ -37,8 +34,8 @@ __device__ __forceinline__ int find_stage(const int* first, int n, int tile) {
 
 template <int TYPE>
 struct GroupSmem {
-    static constexpr int value = TYPE == kStLevelAna ? LA::SMEM
-                                 : TYPE == kStLevelSyn ? LS::SMEM
+    static constexpr int value = (TYPE == kStLevelAna || TYPE == kStLevelAnaQ) ? LA::SMEM
+                                 : (TYPE == kStLevelSyn || TYPE == kStLevelSynQ) ? LS::SMEM
                                  : (TYPE == kStPartial || TYPE == kStQuantize) ? 2 * NT / 64
                                                                                : 1;
 };
@@ -50,24 +47,25 @@ __global__ __launch_bounds__(NT) void group_kernel(const StageDesc* stages, cons
     const int s = find_stage(first, n, t);
     const int tile = t - first[s];
     const StageDesc& d = stages[s];
-    if constexpr (TYPE == kStLevelAna) {
+    constexpr bool Q = TYPE >= kStLevelAnaQ;
+    if constexpr (TYPE == kStLevelAna || TYPE == kStLevelAnaQ) {
         LA st(d.u.la);
-        st.template run_tile<false>(tile, smem);
-    } else if constexpr (TYPE == kStLevelSyn) {
+        st.template run_tile<Q>(tile, smem);
+    } else if constexpr (TYPE == kStLevelSyn || TYPE == kStLevelSynQ) {
         LS st(d.u.ls);
-        st.template run_tile<false>(tile, smem);
-    } else if constexpr (TYPE == kStSplit1Ana) {
+        st.template run_tile<Q>(tile, smem);
+    } else if constexpr (TYPE == kStSplit1Ana || TYPE == kStSplit1AnaQ) {
         S1A st(d.u.sp, d.batch, d.lift);
-        st.template run_tile<false>(tile);
-    } else if constexpr (TYPE == kStSplit2Ana) {
+        st.template run_tile<Q>(tile);
+    } else if constexpr (TYPE == kStSplit2Ana || TYPE == kStSplit2AnaQ) {
         S2A st(d.u.sp, d.batch, d.lift);
-        st.template run_tile<false>(tile);
-    } else if constexpr (TYPE == kStSplit1Syn) {
+        st.template run_tile<Q>(tile);
+    } else if constexpr (TYPE == kStSplit1Syn || TYPE == kStSplit1SynQ) {
         S1S st(d.u.sp, d.batch, d.lift);
-        st.template run_tile<false>(tile);
-    } else if constexpr (TYPE == kStSplit2Syn) {
+        st.template run_tile<Q>(tile);
+    } else if constexpr (TYPE == kStSplit2Syn || TYPE == kStSplit2SynQ) {
         S2S st(d.u.sp, d.batch, d.lift);
-        st.template run_tile<false>(tile);
+        st.template run_tile<Q>(tile);
     } else if constexpr (TYPE == kStPartial) {
         qstage::lowpass_partial<NT>(d.u.q, tile, smem);
     } else if constexpr (TYPE == kStQuantize) {
@@ -98,6 +96,12 @@ hipError_t launch_group(int type, const StageDesc* stages, const int* first, int
         case kStPartial: return launch_type<kStPartial>(stages, first, n, tiles, st);
         case kStQuantize: return launch_type<kStQuantize>(stages, first, n, tiles, st);
         case kStDequantize: return launch_type<kStDequantize>(stages, first, n, tiles, st);
+        case kStLevelAnaQ: return launch_type<kStLevelAnaQ>(stages, first, n, tiles, st);
+        case kStLevelSynQ: return launch_type<kStLevelSynQ>(stages, first, n, tiles, st);
+        case kStSplit1AnaQ: return launch_type<kStSplit1AnaQ>(stages, first, n, tiles, st);
+        case kStSplit2AnaQ: return launch_type<kStSplit2AnaQ>(stages, first, n, tiles, st);
+        case kStSplit1SynQ: return launch_type<kStSplit1SynQ>(stages, first, n, tiles, st);
+        case kStSplit2SynQ: return launch_type<kStSplit2SynQ>(stages, first, n, tiles, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -244,11 +244,12 @@ void free_plan(ct_plan* p) {
     delete p;
 }
 
-int check_stream(const ct_stream_desc& d, Geometry* g) {
+int check_stream(const ct_stream_desc& d, Geometry* g, bool fused) {
     int rc = resolve(&d.geom, g);
     if (rc != CT_OK) return rc;
     if (d.batch < 1 || d.batch > 65535) return CT_ERR_ARG;
-    if (!d.planes || !d.coeffs || !d.idx || !d.side || !d.steps || !d.deq || !d.out) return CT_ERR_ARG;
+    if (!d.planes || !d.idx || !d.side || !d.steps || !d.out) return CT_ERR_ARG;
+    if (!fused && (!d.coeffs || !d.deq)) return CT_ERR_ARG;
     if (d.steps_stride < 0 || (d.steps_stride > 0 && d.steps_stride < g->nsub)) return CT_ERR_ARG;
     return CT_OK;
 }
@@ -270,7 +271,7 @@ int ct_plan_create(const ct_stream_desc* streams, int32_t n, int32_t flags, ct_p
     p->grouping.assign(size_t(n) * kMaxLevels, 2);
     size_t total = 0;
     for (int s = 0; s < n; ++s) {
-        const int rc = check_stream(streams[s], &p->geoms[s]);
+        const int rc = check_stream(streams[s], &p->geoms[s], (flags & CT_PLAN_FUSED) != 0);
         if (rc != CT_OK) {
             free_plan(p);
             return rc;
@@ -304,16 +305,30 @@ int ct_plan_create(const ct_stream_desc* streams, int32_t n, int32_t flags, ct_p
         char* ws = p->ws + p->ws_off[s];
         std::vector<StageDesc>& c = p->chains[s];
         const int* grp = &p->grouping[size_t(s) * kMaxLevels];
-        build_transform_chain(g, d.batch, kModeForward, d.planes, d.coeffs, ws, p->wls[s], grp, c);
-        int rc = build_quant_chain(g, d.batch, d.coeffs, d.steps, d.steps_stride, d.idx, d.side, ws,
+        int rc = CT_OK;
+        if (flags & CT_PLAN_FUSED) {
+            // fused encoder and decoder: no dequantised float coefficients;
+            // the float coefficients only when the caller asks for them
+            const FusedQuant fq{d.idx, d.steps, d.steps_stride, d.side};
+            build_transform_chain(g, d.batch, kModeForward, d.planes, d.coeffs, ws, p->wls[s], grp, c, &fq);
+            const float* low = d.coeffs ? d.coeffs : reinterpret_cast<const float*>(ws + p->wls[s].low_off);
+            rc = build_lowpass_quant_chain(g, d.batch, low, d.coeffs ? g.ncoef : g.low_n, d.steps,
+                                           d.steps_stride, d.idx, d.side, ws, p->wls[s], c);
+            if (rc == CT_OK)
+                build_transform_chain(g, d.batch, kModeInverse, nullptr, d.out, ws, p->wls[s], grp, c, &fq);
+        } else {
+            build_transform_chain(g, d.batch, kModeForward, d.planes, d.coeffs, ws, p->wls[s], grp, c);
+            rc = build_quant_chain(g, d.batch, d.coeffs, d.steps, d.steps_stride, d.idx, d.side, ws,
                                    p->wls[s], c);
-        if (rc == CT_OK)
-            rc = build_dequant_chain(g, d.batch, d.idx, d.steps, d.steps_stride, d.side, d.deq, c);
+            if (rc == CT_OK)
+                rc = build_dequant_chain(g, d.batch, d.idx, d.steps, d.steps_stride, d.side, d.deq, c);
+            if (rc == CT_OK)
+                build_transform_chain(g, d.batch, kModeInverse, d.deq, d.out, ws, p->wls[s], grp, c);
+        }
         if (rc != CT_OK) {
             free_plan(p);
             return rc;
         }
-        build_transform_chain(g, d.batch, kModeInverse, d.deq, d.out, ws, p->wls[s], grp, c);
         max_len = std::max(max_len, c.size());
     }
     // groups: chain position by chain position, one group per stage type,

@@ -64,6 +64,7 @@ class PlanInfo(ctypes.Structure):
 
 PLAN_GRAPH = 1
 PLAN_AUTOTUNE = 2
+PLAN_FUSED = 4
 
 
 class CTError(RuntimeError):
@@ -310,15 +311,16 @@ def inverse(coeffs, height, width, levels, dirs):
 
 
 class Batched:
-    """Many streams of uneven geometry in one persistent launch (ct_plan_*).
+    """Many streams of uneven geometry in one graph launch (ct_plan_*).
 
     streams: list of dicts with keys height, width, levels, dirs, planes
     ([batch, H, W] float32 CUDA tensor) and steps ([nsub] or [batch, nsub]
     float32 CUDA tensor). Output buffers are allocated here and exposed per
-    stream as coeffs, idx, side, deq, out.
+    stream as coeffs, idx, side, deq, out. With fused=True the plan runs the
+    fused encoder and decoder: coeffs and deq are None (not written).
     """
 
-    def __init__(self, streams, graph=True, autotune=False, device="cuda"):
+    def __init__(self, streams, graph=True, autotune=False, device="cuda", fused=False):
         self.device = torch.device(device)
         self.streams = []
         descs = (StreamDesc * len(streams))()
@@ -330,26 +332,27 @@ class Batched:
             n = int(lay.ncoef)
             steps = st["steps"].contiguous()
             stride = 0 if steps.dim() == 1 else int(lay.nsub)
+            flt = None if fused else torch.empty((B, n), dtype=torch.float32, device=self.device)
             rec = dict(height=H, width=W, levels=J, dirs=list(dirs), batch=B, ncoef=n,
                        planes=planes.contiguous(), steps=steps,
-                       coeffs=torch.empty((B, n), dtype=torch.float32, device=self.device),
+                       coeffs=flt,
                        idx=torch.empty((B, n), dtype=torch.int16, device=self.device),
                        side=torch.empty((B, 2), dtype=torch.float32, device=self.device),
-                       deq=torch.empty((B, n), dtype=torch.float32, device=self.device),
+                       deq=None if fused else torch.empty((B, n), dtype=torch.float32, device=self.device),
                        out=torch.empty((B, H, W), dtype=torch.float32, device=self.device))
             self.streams.append(rec)
             d = descs[i]
             d.geom = geom(H, W, J, dirs)
             d.batch = B
             d.planes = rec["planes"].data_ptr()
-            d.coeffs = rec["coeffs"].data_ptr()
+            d.coeffs = rec["coeffs"].data_ptr() if rec["coeffs"] is not None else None
             d.idx = rec["idx"].data_ptr()
             d.side = rec["side"].data_ptr()
             d.steps = steps.data_ptr()
             d.steps_stride = stride
-            d.deq = rec["deq"].data_ptr()
+            d.deq = rec["deq"].data_ptr() if rec["deq"] is not None else None
             d.out = rec["out"].data_ptr()
-        flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0)
+        flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0) | (PLAN_FUSED if fused else 0)
         handle = ctypes.c_void_p()
         torch.cuda.synchronize(self.device)
         _check("ct_plan_create", _lib().ct_plan_create(descs, len(streams), flags, ctypes.byref(handle)))

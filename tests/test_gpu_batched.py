@@ -45,7 +45,8 @@ def _streams(seed=0):
 
 
 def _snapshot(plan):
-    return [{k: s[k].clone() for k in ("coeffs", "idx", "side", "deq", "out")} for s in plan.streams]
+    return [{k: s[k].clone() for k in ("coeffs", "idx", "side", "deq", "out") if s[k] is not None}
+            for s in plan.streams]
 
 
 def _same(a, b):
@@ -145,3 +146,28 @@ def test_autotuned_plan(tmp_path, monkeypatch):
         # the other side of a rounding boundary
         assert (x["idx"] != y["idx"]).float().mean().item() < 1e-4
     ref.close()
+
+
+def test_fused_plan_equals_encode_decode():
+    """A fused plan (grouped launches, one graph) gives each stream exactly
+    what ct_encode and ct_decode give it alone, and its plain launches the
+    same again."""
+    from paper_1510_00561_amd import ct
+    streams = _streams(4)
+    plan = ct.Batched(streams, graph=True, fused=True)
+    assert all(s["coeffs"] is None and s["deq"] is None for s in plan.streams)
+    plan.run()
+    torch.cuda.synchronize()
+    graph = _snapshot(plan)
+    plan.run_plain()
+    torch.cuda.synchronize()
+    _same(graph, _snapshot(plan))
+    for (H, W, J, dirs, B), s, g in zip(STREAMS, plan.streams, graph):
+        print(f"[batched] fused {H}x{W} J={J} dirs={dirs}", flush=True)
+        single = ct.Plan(H, W, J, dirs, B, "cuda")
+        idx, side = single.encode(s["planes"], s["steps"])
+        out = single.decode(idx, s["steps"], side)
+        torch.cuda.synchronize()
+        assert torch.equal(g["idx"], idx) and torch.equal(g["side"], side)
+        assert torch.equal(g["out"], out)
+    plan.close()
