@@ -182,7 +182,10 @@ int split_block_rows(const SplitArgs& a, int batch, int levels) {
     const int t = a.t, vw = stream_cols(levels);
     const int nrh = a.Rj >> (t - 2), nch = a.Cj >> 1, nrv = a.Cj >> (t - 2), ncv = a.Rj >> 1;
     const int cols = (1 << (t - 2)) * ((nch + vw - 1) / vw + (ncv + vw - 1) / vw) * batch;
-    return block_rows(nrh > nrv ? nrh : nrv, cols, resident_waves(), 32, stream_max_rows(levels), 4);
+    // one-level passes carry a small halo and few instructions per row: they
+    // run fastest with shorter blocks and four times as many wavefronts
+    const int slots = levels == 1 ? 4 * resident_waves() : resident_waves();
+    return block_rows(nrh > nrv ? nrh : nrv, cols, slots, 32, stream_max_rows(levels), 4);
 }
 
 // Subband index of the first subband of LP level j in the coefficient layout

@@ -70,6 +70,18 @@ __device__ __forceinline__ int pmod(int i, int n) {
     return r < 0 ? r + n : r;
 }
 
+// Accesses at a wave-uniform base plus a 32-bit per-lane byte offset: the
+// address form with the base in scalar registers and the offset in one
+// vector register, so no per-lane 64-bit address arithmetic is needed.
+template <class T>
+__device__ __forceinline__ T ld_at(const T* base, uint32_t byte_off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void st_at(T* base, uint32_t byte_off, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
 template <int LEVELS, bool ANA, int NT>
 struct StreamSplit {
     static constexpr int WAVES = NT / 64;

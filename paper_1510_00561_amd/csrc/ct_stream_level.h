@@ -152,9 +152,9 @@ struct StreamLevelAna {
                 mr = 0u;
                 g = 0;
             }
-            const char* rp = reinterpret_cast<const char*>(sp + int64_t(g) * A.src.ld);
-            X.x = __uint_as_float(*reinterpret_cast<const uint32_t*>(rp + sc[0]) & (mr & mc[0]));
-            X.y = __uint_as_float(*reinterpret_cast<const uint32_t*>(rp + sc[1]) & (mr & mc[1]));
+            const uint32_t* rp = reinterpret_cast<const uint32_t*>(sp + int64_t(g) * A.src.ld);
+            X.x = __uint_as_float(ld_at(rp, sc[0]) & (mr & mc[0]));
+            X.y = __uint_as_float(ld_at(rp, sc[1]) & (mr & mc[1]));
             xrow = xrow + 1 == R ? 0 : xrow + 1;
         };
 
@@ -174,6 +174,7 @@ struct StreamLevelAna {
         const float* qst = qout ? A.q.steps + int64_t(b) * A.q.steps_stride + A.q.sub0 : nullptr;
         const float d0 = qout ? qst[0] : 1.f, d1 = qout ? qst[1] : 1.f;
         const float d2 = qout ? qst[2] : 1.f, d3 = qout ? qst[3] : 1.f;
+        const uint32_t kc4 = 4u * uint32_t(kc), kc2 = 2u * uint32_t(kc);   // owning lanes: kc >= 0
 
         // transposed flush of `cnt` compact rows starting at compact row i0:
         // four compact columns per instruction, VB rows each
@@ -182,20 +183,25 @@ struct StreamLevelAna {
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const int li = lane & (VB - 1), lk = lane >> 4;
+            // element offset of the lane's first stored (column, row) within
+            // a channel, column (cb0 >> 1) + HC / 2 + lk >= 0 (a channel holds
+            // fewer than 2^28 elements, so byte offsets fit 32 bits); group kk
+            // adds (kk - HC / 2) Rh
+            const uint32_t lo = uint32_t((cb0 >> 1) + HC / 2 + lk) * uint32_t(Rh) + uint32_t(li);
 #pragma unroll
             for (int kk = HC / 2; kk < 64 - HC / 2; kk += 4) {
                 const int l = kk + lk;
                 const int k = (cb0 >> 1) + l;
                 if (li < cnt && k < Ch) {
-                    const int64_t o = int64_t(k) * Rh + i0 + li;
+                    const int64_t ob = int64_t(kk - HC / 2) * Rh + i0;   // wave-uniform part
                     const float a = T[l * VLD + li], e = T[(64 + l) * VLD + li];
                     if (fout) {
-                        q2[o] = a;
-                        q3[o] = e;
+                        st_at(q2 + ob, 4u * lo, a);
+                        st_at(q3 + ob, 4u * lo, e);
                     }
                     if (qout) {
-                        x0[2 * q4 + o] = qstage::to_index(__fdiv_rn(a, d2));
-                        x0[3 * q4 + o] = qstage::to_index(__fdiv_rn(e, d3));
+                        st_at(x0 + 2 * q4 + ob, 2u * lo, qstage::to_index(__fdiv_rn(a, d2)));
+                        st_at(x0 + 3 * q4 + ob, 2u * lo, qstage::to_index(__fdiv_rn(e, d3)));
                     }
                 }
             }
@@ -236,7 +242,7 @@ struct StreamLevelAna {
                 const float cv = col_lowpass<LO_R>(A.lo, h);
                 {
                     const int s = (S >> 1) + n - 2;
-                    if (own && s >= (rb >> 1) && s < (re >> 1)) cp[int64_t(s) * A.c_out.ld + kc] = cv;
+                    if (own && s >= (rb >> 1) && s < (re >> 1)) st_at(cp + int64_t(s) * A.c_out.ld, kc4, cv);
                 }
                 uh[cslot(u - 2)] = row_upsample<UP_R>(A.up, cv);
                 // bandpass rows 2m, 2m + 1 with m = n - 4
@@ -295,14 +301,14 @@ struct StreamLevelAna {
                         const Pair E = dr[rslot(2 * u - 16)], O = dr[rslot(2 * u - 15)];
                         if (own) {
                             const float a = s0 * E.y, e = s1 * O.x;
-                            const int64_t o = int64_t(i) * Ch + kc;
+                            const int64_t o = int64_t(i) * Ch;
                             if (fout) {
-                                q0[o] = a;
-                                q1[o] = e;
+                                st_at(q0 + o, kc4, a);
+                                st_at(q1 + o, kc4, e);
                             }
                             if (qout) {
-                                x0[o] = qstage::to_index(__fdiv_rn(a, d0));
-                                x0[q4 + o] = qstage::to_index(__fdiv_rn(e, d1));
+                                st_at(x0 + o, kc2, qstage::to_index(__fdiv_rn(a, d0)));
+                                st_at(x0 + q4 + o, kc2, qstage::to_index(__fdiv_rn(e, d1)));
                             }
                         }
                         const int slot = (i - (rb >> 1)) & (VB - 1);
@@ -398,6 +404,7 @@ struct StreamLevelSyn {
         const bool own = lane >= HC / 2 && lane < 64 - HC / 2;
         const int j0 = cb0 + 2 * lane;                   // image columns j0, j0 + 1
         const bool st0 = own && j0 < ow, st1 = own && j0 + 1 < ow;
+        const uint32_t j4 = 4u * uint32_t(j0);           // used by storing lanes only (j0 >= 0)
 
         // the four channels as floats, or (decoder, levels with four
         // directions) as indices dequantised on load
@@ -434,17 +441,21 @@ struct StreamLevelSyn {
         const bool vec_ok = !qin && (Rh & 3) == 0 &&
                             ((reinterpret_cast<uintptr_t>(v2) | reinterpret_cast<uintptr_t>(v3)) & 15) == 0;
         const int cg = lane >> 2, rc = lane & 3;
-        int64_t kcol[4];
+        // element offsets of the lane's four columns within a channel (a
+        // channel holds fewer than 2^28 elements, so byte offsets fit 32 bits)
+        uint32_t kcol[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) kcol[c] = int64_t(pmod((cb0 >> 1) + 16 * c + cg, Ch)) * Rh;
+        for (int c = 0; c < 4; ++c) kcol[c] = uint32_t(pmod((cb0 >> 1) + 16 * c + cg, Ch)) * uint32_t(Rh);
         float stg[NSTAGE];
+        const int16_t* x2 = qin ? x0 + 2 * q4 : nullptr;
+        const int16_t* x3 = qin ? x0 + 3 * q4 : nullptr;
         auto stage_load = [&](int i0) {
             if (vec_ok && i0 >= 0 && i0 + VB <= Rh) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const int64_t o = kcol[c] + i0 + 4 * rc;
-                    const float4 a = *reinterpret_cast<const float4*>(v2 + o);
-                    const float4 e = *reinterpret_cast<const float4*>(v3 + o);
+                    const uint32_t o = 4u * (kcol[c] + 4 * rc);
+                    const float4 a = ld_at(reinterpret_cast<const float4*>(v2 + i0), o);
+                    const float4 e = ld_at(reinterpret_cast<const float4*>(v3 + i0), o);
                     stg[4 * c + 0] = a.x;
                     stg[4 * c + 1] = a.y;
                     stg[4 * c + 2] = a.z;
@@ -457,15 +468,15 @@ struct StreamLevelSyn {
             } else {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int i = pmod(i0 + 4 * rc + e, Rh);
+                    const uint32_t i = uint32_t(pmod(i0 + 4 * rc + e, Rh));
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
                         if (qin) {
-                            stg[4 * c + e] = __fmul_rn(float(x0[2 * q4 + kcol[c] + i]), d2);
-                            stg[16 + 4 * c + e] = __fmul_rn(float(x0[3 * q4 + kcol[c] + i]), d3);
+                            stg[4 * c + e] = __fmul_rn(float(ld_at(x2, 2u * (kcol[c] + i))), d2);
+                            stg[16 + 4 * c + e] = __fmul_rn(float(ld_at(x3, 2u * (kcol[c] + i))), d3);
                         } else {
-                            stg[4 * c + e] = v2[kcol[c] + i];
-                            stg[16 + 4 * c + e] = v3[kcol[c] + i];
+                            stg[4 * c + e] = ld_at(v2, 4u * (kcol[c] + i));
+                            stg[16 + 4 * c + e] = ld_at(v3, 4u * (kcol[c] + i));
                         }
                     }
                 }
@@ -492,24 +503,25 @@ struct StreamLevelSyn {
         int crow = pmod(S2 - 6, Rh);        // next lowpass row
         Pair hn;                            // prefetched H values of the next compact row
         float cn;                           // prefetched lowpass value
+        const uint32_t kcw4 = 4u * uint32_t(kcw), kcw2 = 2u * uint32_t(kcw);
         auto load_h = [&]() {
-            const int64_t o = int64_t(hrow) * Ch + kcw;
+            const int64_t o = int64_t(hrow) * Ch;
             if (qin) {
-                hn.x = __fmul_rn(float(x0[q4 + o]), d1);   // odd row, even column
-                hn.y = __fmul_rn(float(x0[o]), d0);        // even row, odd column
+                hn.x = __fmul_rn(float(ld_at(x0 + q4 + o, kcw2)), d1);   // odd row, even column
+                hn.y = __fmul_rn(float(ld_at(x0 + o, kcw2)), d0);        // even row, odd column
             } else {
-                hn.x = h1[o];
-                hn.y = h0[o];
+                hn.x = ld_at(h1 + o, kcw4);
+                hn.y = ld_at(h0 + o, kcw4);
             }
             hrow = hrow + 1 == Rh ? 0 : hrow + 1;
         };
         auto load_c = [&]() {
             if (lin) {
                 // the lowpass dequantised as ct_dequantize does
-                const float w = __fmul_rn(float(lx[int64_t(crow) * A.c_in.ld + kcw]), l_step);
+                const float w = __fmul_rn(float(ld_at(lx + int64_t(crow) * A.c_in.ld, kcw2)), l_step);
                 cn = __fadd_rn(l_mn, __fmul_rn(w, l_r));
             } else {
-                cn = cin[int64_t(crow) * A.c_in.ld + kcw];
+                cn = ld_at(cin + int64_t(crow) * A.c_in.ld, kcw4);
             }
             crow = crow + 1 == Rh ? 0 : crow + 1;
         };
@@ -607,13 +619,13 @@ struct StreamLevelSyn {
                     const int r = 2 * S2 + 2 * n - LAG;          // image row of de
                     if (r >= rb && r < re && r < oh) {
                         float* rp = xo + int64_t(r) * A.x_out.ld;
-                        if (st0) rp[j0] = de.x + ex;
-                        if (st1) rp[j0 + 1] = de.y + ey;
+                        if (st0) st_at(rp, j4, de.x + ex);
+                        if (st1) st_at(rp, j4 + 4u, de.y + ey);
                     }
                     if (r + 1 >= rb && r + 1 < re && r + 1 < oh) {
                         float* rp = xo + int64_t(r + 1) * A.x_out.ld;
-                        if (st0) rp[j0] = dod.x + ox;
-                        if (st1) rp[j0 + 1] = dod.y + oy;
+                        if (st0) st_at(rp, j4, dod.x + ox);
+                        if (st1) st_at(rp, j4 + 4u, dod.y + oy);
                     }
                 }
             }
