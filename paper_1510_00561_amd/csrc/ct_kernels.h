@@ -107,8 +107,11 @@ __host__ __device__ inline int block_rows(int rows, int col_items, int slots, in
 // levels per pass): every wavefront stores a strip of stream_cols() sheared
 // columns by SplitArgs::bh rows of one parent channel, and loads a halo of
 // stream_halo() rows and columns around it.
+__host__ __device__ constexpr int stream_cols_per_lane() { return 2; }
 __host__ __device__ constexpr int stream_halo(int levels) { return levels == 1 ? 4 : 12; }
-__host__ __device__ constexpr int stream_cols(int levels) { return 128 - 2 * stream_halo(levels); }
+__host__ __device__ constexpr int stream_cols(int levels) {
+    return 64 * stream_cols_per_lane() - 2 * stream_halo(levels);
+}
 __host__ __device__ constexpr int stream_max_rows(int levels) { return levels == 1 ? 248 : 216; }
 
 // Per plane: horizontal parents first (each with `ih` items, `sh` strips

@@ -1,7 +1,7 @@
 // Register-streaming form of the deeper DFB tree levels (t >= 3), one tree
 // level or two consecutive ones per pass.
 //
-// Every wavefront owns one strip of 128 sheared columns (two adjacent
+// Every wavefront owns one strip of 256 sheared columns (four adjacent
 // columns per lane) of one parent channel and streams down a block of its
 // rows. Rows live in a ring of registers; a lifting step on a row reads its
 // vertical neighbours from the ring and its horizontal neighbours from the
@@ -45,24 +45,41 @@ __device__ __forceinline__ float from_prev(float v) {
 }
 
 struct Pair {
-    float x, y;   // sheared columns k0 and k0 + 1 of this lane
+    float x, y;   // columns k0 and k0 + 1 of this lane
 };
 
-// Level-t step on row X from its upper (U) and lower (V) neighbours, or the
-// odd-row level-(t+1) step with U, V two rows away.
-__device__ __forceinline__ void step_near(Pair& X, const Pair& U, const Pair& V, float c) {
-    const float vp = from_prev(V.y);   // V[k0 - 1]
-    const float un = from_next(U.x);   // U[k0 + 2]
-    X.x = fmaf(c, (U.y + vp) - (U.x + V.x), X.x);
-    X.y = fmaf(c, (un + V.x) - (U.y + V.y), X.y);
+// N adjacent sheared columns of one lane (lane l holds columns N l .. N l + N - 1).
+template <int N>
+struct Cols {
+    float v[N];
+};
+
+// Column e of the lane's row, e in [-N, 2N): the lane's own value or that of
+// the previous / next lane (the steps below only call it with constants).
+template <int N>
+__device__ __forceinline__ float col(const Cols<N>& a, int e) {
+    if (e < 0) return from_prev(a.v[e + N]);
+    if (e >= N) return from_next(a.v[e - N]);
+    return a.v[e];
 }
 
-// Even-row level-(t+1) step.
-__device__ __forceinline__ void step_far(Pair& X, const Pair& U, const Pair& V, float c) {
-    const float un0 = from_next(U.x), un1 = from_next(U.y);   // U[k0 + 2], U[k0 + 3]
-    const float vp0 = from_prev(V.x), vp1 = from_prev(V.y);   // V[k0 - 2], V[k0 - 1]
-    X.x = fmaf(c, (un0 + vp0) - (U.y + vp1), X.x);
-    X.y = fmaf(c, (un1 + vp1) - (un0 + V.x), X.y);
+// Level-t step on row X from its upper (U) and lower (V) neighbours, or the
+// odd-row level-(t+1) step with U, V two rows away:
+// X[k] += c ((U[k+1] + V[k-1]) - (U[k] + V[k])).
+template <int N>
+__device__ __forceinline__ void step_near(Cols<N>& X, const Cols<N>& U, const Cols<N>& V, float c) {
+#pragma unroll
+    for (int e = 0; e < N; ++e)
+        X.v[e] = fmaf(c, (col(U, e + 1) + col(V, e - 1)) - (U.v[e] + V.v[e]), X.v[e]);
+}
+
+// Even-row level-(t+1) step:
+// X[k] += c ((U[k+2] + V[k-2]) - (U[k+1] + V[k-1])).
+template <int N>
+__device__ __forceinline__ void step_far(Cols<N>& X, const Cols<N>& U, const Cols<N>& V, float c) {
+#pragma unroll
+    for (int e = 0; e < N; ++e)
+        X.v[e] = fmaf(c, (col(U, e + 2) + col(V, e - 2)) - (col(U, e + 1) + col(V, e - 1)), X.v[e]);
 }
 
 __device__ __forceinline__ int pmod(int i, int n) {
@@ -82,15 +99,30 @@ __device__ __forceinline__ void st_at(T* base, uint32_t byte_off, T v) {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
+// N consecutive elements at a 4-byte aligned address as one access (global
+// memory accesses of several dwords need only dword alignment).
+template <int N, class T>
+__device__ __forceinline__ void ld_vec(const T* base, uint32_t byte_off, T (&v)[N]) {
+    __builtin_memcpy(v, __builtin_assume_aligned(reinterpret_cast<const char*>(base) + byte_off, 4), sizeof(T) * N);
+}
+template <int N, class T>
+__device__ __forceinline__ void st_vec(T* base, uint32_t byte_off, const T (&v)[N]) {
+    __builtin_memcpy(__builtin_assume_aligned(reinterpret_cast<char*>(base) + byte_off, 4), v, sizeof(T) * N);
+}
+
 template <int LEVELS, bool ANA, int NT>
 struct StreamSplit {
     static constexpr int WAVES = NT / 64;
+    static constexpr int CPL = stream_cols_per_lane();     // adjacent columns per lane
+    using Row = Cols<CPL>;
     static constexpr int TL = stream_halo(LEVELS);         // total lag = halo rows = halo columns
     static constexpr int HC = TL;
     static constexpr int VW = stream_cols(LEVELS);         // stored columns per strip
-    // ring rows (multiple of 4): the rows the steps still read, plus two
-    // supersteps of prefetched rows
-    static constexpr int RING = LEVELS == 1 ? 20 : 28;
+    // supersteps of prefetched rows; ring rows (multiple of 4): the rows the
+    // steps and stores still read (up to TL + 2 behind the superstep's first
+    // row), the superstep's rows and the prefetched ones
+    static constexpr int PF = 2;
+    static constexpr int RING = (TL + 2 + 4 + 4 * PF + 3) / 4 * 4;
     static constexpr int UNROLL = RING / 4;
     static constexpr int NSTEP = 4 * LEVELS;
 
@@ -154,12 +186,21 @@ struct StreamSplit {
         const int kb = strip * VW, rb = blk * A.bh;
         const int ke = min(kb + VW, nc), re = min(rb + A.bh, nr);
         const int lane = threadIdx.x & 63;
-        // byte offsets of the lane's two columns modulo the row, relative to
-        // the row's column base (kb - HC - a i) mod nc
+        // byte offsets of the lane's columns modulo the row, relative to the
+        // row's column base (kb - HC - a i) mod nc, and whether the lane
+        // stores them (halo columns are not stored)
         const uint32_t ncb = 4u * uint32_t(nc);
-        const uint32_t m0 = 4u * uint32_t(pmod(2 * lane, nc)), m1 = 4u * uint32_t(pmod(2 * lane + 1, nc));
-        const int kl = kb - HC + 2 * lane;
-        const bool st0 = kl >= kb && kl < ke, st1 = kl + 1 >= kb && kl + 1 < ke;
+        const int kl = kb - HC + CPL * lane;
+        uint32_t m[CPL];
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) m[e] = 4u * uint32_t(pmod(CPL * lane + e, nc));
+        // HC and kb are multiples of CPL, so a lane's columns are all halo or
+        // all stored. Only the lane holding column ke - 1 of a row's last strip
+        // can reach past ke: its extra columns lie below kb + VW, so they are
+        // exact values of the row's first columns (modulo nc), which it then
+        // stores once more with the same bits as the first strip.
+        static_assert(HC % CPL == 0 && VW % CPL == 0, "strip geometry");
+        const bool st_in = kl >= kb && kl < ke;
         const int S = rb - TL;                      // first loaded row (S = 0 mod 4)
         const int E = S - TL;                       // row leaving the pipeline at superstep 0
         const int NS = (re - rb + 3) / 4 + TL / 2;  // supersteps that matter
@@ -215,28 +256,62 @@ struct StreamSplit {
         constexpr int LSH = ANA ? 0 : CSH;
         constexpr int SSH = ANA ? CSH : 0;
 
-        Pair w[RING];
+        Row w[RING];
 #pragma unroll
-        for (int r = 0; r < RING; ++r) w[r] = Pair{0.f, 0.f};
+        for (int r = 0; r < RING; ++r)
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) w[r].v[e] = 0.f;
 
-        auto load4 = [&](int u_next) {
+        // byte offset of column e for a row with column base cb (bytes)
+        auto colofs = [&](int cb, int e) __attribute__((always_inline)) {
+            const uint32_t o = uint32_t(cb) + m[e];
+            return min(o, o - ncb);
+        };
+        // A lane's CPL columns are consecutive in memory unless they straddle
+        // the end of the row. Row class r has a fixed column base modulo CPL
+        // (its base moves by 4 a columns per superstep): when that is 0 and
+        // CPL divides nc, no lane straddles; otherwise only a row whose strip
+        // wraps can have one. Such rows take per-column accesses; all others
+        // move a lane's columns (and, when aligned, its indices) at once.
+        bool lal[4], sal[4], qal[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            lal[r] = nc % CPL == 0 && (lcb[r] >> 2) % CPL == 0;
+            sal[r] = nc % CPL == 0 && (scb[r] >> 2) % CPL == 0;
+            // indices move CPL at once only from dword-aligned addresses
+            qal[r] = (reinterpret_cast<uintptr_t>(qbase[r]) & 3) == 0;
+        }
+        constexpr uint32_t STRIP_BYTES = 4u * CPL * 64u;
+        auto load4 = [&](int u_next) __attribute__((always_inline)) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const char* rp = (!ANA && QUANT) ? nullptr
-                                 : reinterpret_cast<const char*>(lbase[r] + int64_t(lrow[r] >> LSH) * nc);
-                uint32_t o0 = uint32_t(lcb[r]) + m0, o1 = uint32_t(lcb[r]) + m1;
-                o0 = min(o0, o0 - ncb);
-                o1 = min(o1, o1 - ncb);
-                Pair& X = w[slot(4 * u_next + r)];
+                Row& X = w[slot(4 * u_next + r)];
+                const int64_t ro = int64_t(lrow[r] >> LSH) * nc;
+                const int cb = lcb[r];
                 if (!ANA && QUANT) {
                     // dequantise on load: (q * step) * scale, as ct_dequantize
                     // followed by a float load would compute
-                    const int16_t* qr = qbase[r] + int64_t(lrow[r] >> LSH) * nc;
-                    X.x = lsc[r] * __fmul_rn(float(qr[o0 >> 2]), qstep[r]);
-                    X.y = lsc[r] * __fmul_rn(float(qr[o1 >> 2]), qstep[r]);
+                    const int16_t* qr = qbase[r] + ro;
+                    int16_t q[CPL];
+                    if (lal[r] && qal[r]) {
+                        ld_vec<CPL>(qr, colofs(cb, 0) >> 1, q);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < CPL; ++e) q[e] = ld_at(qr, colofs(cb, e) >> 1);
+                    }
+#pragma unroll
+                    for (int e = 0; e < CPL; ++e) X.v[e] = lsc[r] * __fmul_rn(float(q[e]), qstep[r]);
                 } else {
-                    X.x = lsc[r] * *reinterpret_cast<const float*>(rp + o0);
-                    X.y = lsc[r] * *reinterpret_cast<const float*>(rp + o1);
+                    const float* rp = lbase[r] + ro;
+                    float x[CPL];
+                    if (lal[r] || uint32_t(cb) + STRIP_BYTES <= ncb) {
+                        ld_vec<CPL>(rp, colofs(cb, 0), x);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < CPL; ++e) x[e] = ld_at(rp, colofs(cb, e));
+                    }
+#pragma unroll
+                    for (int e = 0; e < CPL; ++e) X.v[e] = lsc[r] * x[e];
                 }
                 lrow[r] += r4;
                 lrow[r] = lrow[r] >= nr ? lrow[r] - nr : lrow[r];
@@ -244,42 +319,57 @@ struct StreamSplit {
                 lcb[r] = lcb[r] < 0 ? lcb[r] + int(ncb) : lcb[r];
             }
         };
-        auto store4 = [&](int u, int n) {
+        auto store4 = [&](int u, int n) __attribute__((always_inline)) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = E + 4 * n + r;
-                uint32_t o0 = uint32_t(scb[r]) + m0, o1 = uint32_t(scb[r]) + m1;
-                o0 = min(o0, o0 - ncb);
-                o1 = min(o1, o1 - ncb);
+                const int cb = scb[r];
                 scb[r] -= a4b;
                 scb[r] = scb[r] < 0 ? scb[r] + int(ncb) : scb[r];
                 if (i < rb || i >= re) continue;
-                const Pair& X = w[slot(4 * u - TL + r)];
-                const float v0 = ssc[r] * X.x, v1 = ssc[r] * X.y;
-                if (store_float) {
-                    char* rp = reinterpret_cast<char*>(sbase[r] + int64_t(i >> SSH) * nc);
-                    if (st0) *reinterpret_cast<float*>(rp + o0) = v0;
-                    if (st1) *reinterpret_cast<float*>(rp + o1) = v1;
+                const Row& X = w[slot(4 * u - TL + r)];
+                const int64_t ro = int64_t(i >> SSH) * nc;
+                float* fp = store_float ? sbase[r] + ro : nullptr;
+                int16_t* qp = (ANA && QUANT) ? qbase[r] + ro : nullptr;
+                float v[CPL];
+                int16_t qv[CPL];
+#pragma unroll
+                for (int e = 0; e < CPL; ++e) {
+                    v[e] = ssc[r] * X.v[e];
+                    // quantise on store: round(c / step), as ct_quantize on
+                    // the stored float
+                    qv[e] = (ANA && QUANT) ? qstage::to_index(__fdiv_rn(v[e], qstep[r])) : int16_t(0);
                 }
-                if (ANA && QUANT) {
-                    // quantise on store: round(c / step), as ct_quantize on the
-                    // stored float
-                    int16_t* qr = qbase[r] + int64_t(i >> SSH) * nc;
-                    if (st0) qr[o0 >> 2] = qstage::to_index(__fdiv_rn(v0, qstep[r]));
-                    if (st1) qr[o1 >> 2] = qstage::to_index(__fdiv_rn(v1, qstep[r]));
+                const bool fvec = sal[r] || uint32_t(cb) + STRIP_BYTES <= ncb;
+                if (st_in) {
+                    if (store_float) {
+                        if (fvec) {
+                            st_vec<CPL>(fp, colofs(cb, 0), v);
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < CPL; ++e) st_at(fp, colofs(cb, e), v[e]);
+                        }
+                    }
+                    if (ANA && QUANT) {
+                        if (sal[r] && qal[r]) {
+                            st_vec<CPL>(qp, colofs(cb, 0) >> 1, qv);
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < CPL; ++e) st_at(qp, colofs(cb, e) >> 1, qv[e]);
+                        }
+                    }
                 }
             }
         };
 
-        load4(0);
-        load4(1);
+#pragma unroll
+        for (int p = 0; p < PF; ++p) load4(p);
         for (int n0 = 0; n0 < NS; n0 += UNROLL) {
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
-                // the rows of the superstep after next go into ring slots that
-                // no step of this superstep reads (two supersteps of latency
-                // hiding)
-                load4(u + 2);
+                // the rows of superstep u + PF go into ring slots that no step
+                // of this superstep reads (PF supersteps of latency hiding)
+                load4(u + PF);
 #pragma unroll
                 for (int q = 0; q < NSTEP; ++q) apply_step<FO>(w, u, q);
                 store4(u, n0 + u);
@@ -288,7 +378,7 @@ struct StreamSplit {
     }
 
     template <int FO>
-    __device__ __forceinline__ void apply_step(Pair* w, int u, int q) const {
+    __device__ __forceinline__ void apply_step(Row* w, int u, int q) const {
         const StepInfo si = info(q);
         const float c = 0.5f * lift.c[si.s];
         const int cls = (FO + si.s) & 1;
@@ -298,9 +388,9 @@ struct StreamSplit {
             const int m4 = ((j - si.lag) % 4 + 4) % 4; // row index mod 4 (S = 0 mod 4)
             const int rc = si.deep ? (m4 >> 1) & 1 : m4 & 1;
             if (rc != cls) continue;
-            Pair& X = w[slot(rel)];
-            const Pair& U = w[slot(rel - si.d)];
-            const Pair& V = w[slot(rel + si.d)];
+            Row& X = w[slot(rel)];
+            const Row& U = w[slot(rel - si.d)];
+            const Row& V = w[slot(rel + si.d)];
             if (si.deep && (m4 & 1) == 0) step_far(X, U, V, c);
             else step_near(X, U, V, c);
         }
