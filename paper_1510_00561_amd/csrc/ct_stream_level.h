@@ -405,6 +405,7 @@ struct StreamLevelSyn {
         const int j0 = cb0 + 2 * lane;                   // image columns j0, j0 + 1
         const bool st0 = own && j0 < ow, st1 = own && j0 + 1 < ow;
         const uint32_t j4 = 4u * uint32_t(j0);           // used by storing lanes only (j0 >= 0)
+        const bool pair_st = (ow & 1) == 0;
 
         // the four channels as floats, or (decoder, levels with four
         // directions) as indices dequantised on load
@@ -617,16 +618,19 @@ struct StreamLevelSyn {
                     ox = fmaf(A.up.t[3], um1.x + up2.x, ox);
                     oy = fmaf(A.up.t[3], um1.y + up2.y, oy);
                     const int r = 2 * S2 + 2 * n - LAG;          // image row of de
-                    if (r >= rb && r < re && r < oh) {
-                        float* rp = xo + int64_t(r) * A.x_out.ld;
-                        if (st0) st_at(rp, j4, de.x + ex);
-                        if (st1) st_at(rp, j4 + 4u, de.y + ey);
-                    }
-                    if (r + 1 >= rb && r + 1 < re && r + 1 < oh) {
-                        float* rp = xo + int64_t(r + 1) * A.x_out.ld;
-                        if (st0) st_at(rp, j4, dod.x + ox);
-                        if (st1) st_at(rp, j4 + 4u, dod.y + oy);
-                    }
+                    auto put = [&](int row, float a, float c) __attribute__((always_inline)) {
+                        float* rp = xo + int64_t(row) * A.x_out.ld;
+                        if (pair_st) {
+                            // even output width: a lane stores both columns or none
+                            const float v[2] = {a, c};
+                            if (st0) st_vec<2>(rp, j4, v);
+                        } else {
+                            if (st0) st_at(rp, j4, a);
+                            if (st1) st_at(rp, j4 + 4u, c);
+                        }
+                    };
+                    if (r >= rb && r < re && r < oh) put(r, de.x + ex, de.y + ey);
+                    if (r + 1 >= rb && r + 1 < re && r + 1 < oh) put(r + 1, dod.x + ox, dod.y + oy);
                 }
             }
         }
