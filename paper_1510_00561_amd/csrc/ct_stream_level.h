@@ -77,9 +77,9 @@ struct StreamLevelAna {
     static constexpr int VW = level_cols();  // stored image columns per strip (128 - 2 HC)
     static constexpr int TOP = 18;           // rows loaded above a block
     static constexpr int LAG = 16;           // rows from the newest loaded row to the output
-    static constexpr int U = 6;              // supersteps per ring cycle
-    static constexpr int RR = 12;            // ring rows: x, hf and d
-    static constexpr int RC = 6;             // ring rows: uh (lowpass rows)
+    static constexpr int U = 7;              // supersteps per ring cycle
+    static constexpr int RR = 14;            // ring rows: x (two supersteps prefetched), hf and d
+    static constexpr int RC = 7;             // ring rows: uh (lowpass rows)
     static constexpr int VB = 16;            // compact rows per transposed flush
     static constexpr int VLD = VB + 1;
     static constexpr int WAVE_SMEM = 2 * 64 * VLD;
@@ -222,15 +222,15 @@ struct StreamLevelAna {
 #pragma unroll
         for (int r = 0; r < RC; ++r) uh[r] = Pair{0.f, 0.f};
 
-        load_row(xr[0]);
-        load_row(xr[1]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) load_row(xr[r]);
         for (int n0 = 0; n0 < NS; n0 += U) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int n = n0 + u;
-                // prefetch the next pair of rows
-                load_row(xr[rslot(2 * u + 2)]);
-                load_row(xr[rslot(2 * u + 3)]);
+                // prefetch the pair of rows two supersteps ahead
+                load_row(xr[rslot(2 * u + 4)]);
+                load_row(xr[rslot(2 * u + 5)]);
                 // horizontal lowpass of rows 2n, 2n + 1
                 hf[rslot(2 * u)] = row_lowpass<LO_R>(A.lo, xr[rslot(2 * u)].x, xr[rslot(2 * u)].y);
                 hf[rslot(2 * u + 1)] =
@@ -502,28 +502,26 @@ struct StreamLevelSyn {
 
         int hrow = pmod(S2, Rh);            // next compact row of the H channels
         int crow = pmod(S2 - 6, Rh);        // next lowpass row
-        Pair hn;                            // prefetched H values of the next compact row
-        float cn;                           // prefetched lowpass value
+        // H values and lowpass values of the compact rows two supersteps
+        // ahead, as loaded (indices keep their integer bits and are
+        // dequantised where they are used, so nothing waits on a load early)
+        Pair hq[2];
+        float cq[2];
         const uint32_t kcw4 = 4u * uint32_t(kcw), kcw2 = 2u * uint32_t(kcw);
-        auto load_h = [&]() {
+        auto load_h = [&](Pair& hn) {
             const int64_t o = int64_t(hrow) * Ch;
             if (qin) {
-                hn.x = __fmul_rn(float(ld_at(x0 + q4 + o, kcw2)), d1);   // odd row, even column
-                hn.y = __fmul_rn(float(ld_at(x0 + o, kcw2)), d0);        // even row, odd column
+                hn.x = __builtin_bit_cast(float, int(ld_at(x0 + q4 + o, kcw2)));   // odd row, even column
+                hn.y = __builtin_bit_cast(float, int(ld_at(x0 + o, kcw2)));        // even row, odd column
             } else {
                 hn.x = ld_at(h1 + o, kcw4);
                 hn.y = ld_at(h0 + o, kcw4);
             }
             hrow = hrow + 1 == Rh ? 0 : hrow + 1;
         };
-        auto load_c = [&]() {
-            if (lin) {
-                // the lowpass dequantised as ct_dequantize does
-                const float w = __fmul_rn(float(ld_at(lx + int64_t(crow) * A.c_in.ld, kcw2)), l_step);
-                cn = __fadd_rn(l_mn, __fmul_rn(w, l_r));
-            } else {
-                cn = ld_at(cin + int64_t(crow) * A.c_in.ld, kcw4);
-            }
+        auto load_c = [&](float& cn) {
+            if (lin) cn = __builtin_bit_cast(float, int(ld_at(lx + int64_t(crow) * A.c_in.ld, kcw2)));
+            else cn = ld_at(cin + int64_t(crow) * A.c_in.ld, kcw4);
             crow = crow + 1 == Rh ? 0 : crow + 1;
         };
 
@@ -542,8 +540,11 @@ struct StreamLevelSyn {
         stage_store();
         lds_sync();
         stage_load(S2 + VB);
-        load_h();
-        load_c();
+        load_h(hq[0]);
+        load_c(cq[0]);
+        load_h(hq[1]);
+        load_c(cq[1]);
+        static_assert(U % 2 == 0, "prefetch ring");
         for (int n0 = 0; n0 < NS; n0 += U) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -562,13 +563,21 @@ struct StreamLevelSyn {
                     Pair& E = w[rslot(2 * u)];
                     Pair& O = w[rslot(2 * u + 1)];
                     E.x = s2 * T[lane * VLD + ni];
-                    E.y = s0 * hn.y;
-                    O.x = s1 * hn.x;
+                    const Pair& H = hq[u & 1];
+                    const float hx = qin ? __fmul_rn(float(__builtin_bit_cast(int, H.x)), d1) : H.x;
+                    const float hy = qin ? __fmul_rn(float(__builtin_bit_cast(int, H.y)), d0) : H.y;
+                    E.y = s0 * hy;
+                    O.x = s1 * hx;
                     O.y = s3 * T[(64 + lane) * VLD + ni];
                 }
-                const float cv = cn;
-                load_h();
-                load_c();
+                float cv = cq[u & 1];
+                if (lin) {
+                    // the lowpass dequantised as ct_dequantize does
+                    const float w = __fmul_rn(float(__builtin_bit_cast(int, cv)), l_step);
+                    cv = __fadd_rn(l_mn, __fmul_rn(w, l_r));
+                }
+                load_h(hq[u & 1]);
+                load_c(cq[u & 1]);
                 // tree level 2 (q < 4) then level 1, step q on rows 2n - 1 - q, 2n - q
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
