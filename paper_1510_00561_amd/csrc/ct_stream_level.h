@@ -77,9 +77,10 @@ struct StreamLevelAna {
     static constexpr int VW = level_cols();  // stored image columns per strip (128 - 2 HC)
     static constexpr int TOP = 18;           // rows loaded above a block
     static constexpr int LAG = 16;           // rows from the newest loaded row to the output
-    static constexpr int U = 7;              // supersteps per ring cycle
-    static constexpr int RR = 14;            // ring rows: x (two supersteps prefetched), hf and d
-    static constexpr int RC = 7;             // ring rows: uh (lowpass rows)
+    static constexpr int PF = 2;             // supersteps of prefetched input rows
+    static constexpr int U = 5 + PF;         // supersteps per ring cycle
+    static constexpr int RR = 2 * U;         // ring rows: x (12 in use plus the prefetched), hf and d
+    static constexpr int RC = U;             // ring rows: uh (lowpass rows)
     static constexpr int VB = 16;            // compact rows per transposed flush
     static constexpr int VLD = VB + 1;
     static constexpr int WAVE_SMEM = 2 * 64 * VLD;
@@ -223,14 +224,14 @@ struct StreamLevelAna {
         for (int r = 0; r < RC; ++r) uh[r] = Pair{0.f, 0.f};
 
 #pragma unroll
-        for (int r = 0; r < 4; ++r) load_row(xr[r]);
+        for (int r = 0; r < 2 * PF; ++r) load_row(xr[r]);
         for (int n0 = 0; n0 < NS; n0 += U) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int n = n0 + u;
-                // prefetch the pair of rows two supersteps ahead
-                load_row(xr[rslot(2 * u + 4)]);
-                load_row(xr[rslot(2 * u + 5)]);
+                // prefetch the pair of rows PF supersteps ahead
+                load_row(xr[rslot(2 * u + 2 * PF)]);
+                load_row(xr[rslot(2 * u + 2 * PF + 1)]);
                 // horizontal lowpass of rows 2n, 2n + 1
                 hf[rslot(2 * u)] = row_lowpass<LO_R>(A.lo, xr[rslot(2 * u)].x, xr[rslot(2 * u)].y);
                 hf[rslot(2 * u + 1)] =
@@ -350,6 +351,7 @@ struct StreamLevelSyn {
     static constexpr int TOP = 16;           // an output row depends on input rows 15 above it
     static constexpr int LAG = 16;
     static constexpr int U = 10;             // supersteps per ring cycle
+    static constexpr int PFH = 5;            // supersteps of prefetched H and lowpass rows
     static constexpr int RR = 20;            // ring rows: channels / bandpass
     static constexpr int RH = 10;            // ring rows: hf
     static constexpr int RC = 5;             // ring rows: uh (lowpass rows)
@@ -505,8 +507,8 @@ struct StreamLevelSyn {
         // H values and lowpass values of the compact rows two supersteps
         // ahead, as loaded (indices keep their integer bits and are
         // dequantised where they are used, so nothing waits on a load early)
-        Pair hq[2];
-        float cq[2];
+        Pair hq[PFH];
+        float cq[PFH];
         const uint32_t kcw4 = 4u * uint32_t(kcw), kcw2 = 2u * uint32_t(kcw);
         auto load_h = [&](Pair& hn) {
             const int64_t o = int64_t(hrow) * Ch;
@@ -540,11 +542,12 @@ struct StreamLevelSyn {
         stage_store();
         lds_sync();
         stage_load(S2 + VB);
-        load_h(hq[0]);
-        load_c(cq[0]);
-        load_h(hq[1]);
-        load_c(cq[1]);
-        static_assert(U % 2 == 0, "prefetch ring");
+#pragma unroll
+        for (int p = 0; p < PFH; ++p) {
+            load_h(hq[p]);
+            load_c(cq[p]);
+        }
+        static_assert(U % PFH == 0, "prefetch ring");
         for (int n0 = 0; n0 < NS; n0 += U) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -563,21 +566,21 @@ struct StreamLevelSyn {
                     Pair& E = w[rslot(2 * u)];
                     Pair& O = w[rslot(2 * u + 1)];
                     E.x = s2 * T[lane * VLD + ni];
-                    const Pair& H = hq[u & 1];
+                    const Pair& H = hq[u % PFH];
                     const float hx = qin ? __fmul_rn(float(__builtin_bit_cast(int, H.x)), d1) : H.x;
                     const float hy = qin ? __fmul_rn(float(__builtin_bit_cast(int, H.y)), d0) : H.y;
                     E.y = s0 * hy;
                     O.x = s1 * hx;
                     O.y = s3 * T[(64 + lane) * VLD + ni];
                 }
-                float cv = cq[u & 1];
+                float cv = cq[u % PFH];
                 if (lin) {
                     // the lowpass dequantised as ct_dequantize does
                     const float w = __fmul_rn(float(__builtin_bit_cast(int, cv)), l_step);
                     cv = __fadd_rn(l_mn, __fmul_rn(w, l_r));
                 }
-                load_h(hq[u & 1]);
-                load_c(cq[u & 1]);
+                load_h(hq[u % PFH]);
+                load_c(cq[u % PFH]);
                 // tree level 2 (q < 4) then level 1, step q on rows 2n - 1 - q, 2n - q
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
