@@ -83,6 +83,11 @@ int resolve(const ct_geom* g, Geometry* out) {
     if (r.H > 32768 || r.W > 32768) return CT_ERR_GEOM;
     r.R = (r.H + step - 1) / step * step;
     r.C = (r.W + step - 1) / step * step;
+    // Levels with three or more tree levels run split stages on channels of
+    // R_j / 2 or C_j / 2 columns, which they move in column pairs: the choice
+    // of e (>= j + 1 there) keeps R_j and C_j multiples of 4.
+    for (int j = 1; j <= r.J; ++j)
+        if (r.l[j - 1] >= 3 && (((r.R >> (j - 1)) & 3) || ((r.C >> (j - 1)) & 3))) return CT_ERR_GEOM;
     r.low_n = int64_t(r.R >> r.J) * (r.C >> r.J);
     int64_t off = r.low_n;
     r.nsub = 1;

@@ -86,6 +86,7 @@ hipError_t launch_level_synthesis(const stage::LevelSynArgs& a, int lo_r, hipStr
 template <int LEVELS, bool ANA>
 static hipError_t launch_split(const SplitArgs& a, Lift lift, int batch, hipStream_t st) {
     if (a.bh <= 0 || (a.bh & 3)) return hipErrorInvalidValue;
+    if ((a.Rj & 3) || (a.Cj & 3)) return hipErrorInvalidValue;   // channel rows of even width
     constexpr int waves = NT_STREAM / 64;
     const int tiles = (stream_items(a, batch, LEVELS) + waves - 1) / waves;
     if (a.q.idx) stream_split_kernel<LEVELS, ANA, true><<<tiles, NT_STREAM, 0, st>>>(a, lift, batch);

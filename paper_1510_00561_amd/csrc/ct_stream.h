@@ -270,9 +270,13 @@ struct StreamSplit {
         // A lane's CPL columns are consecutive in memory unless they straddle
         // the end of the row. Row class r has a fixed column base modulo CPL
         // (its base moves by 4 a columns per superstep): when that is 0 and
-        // CPL divides nc, no lane straddles; otherwise only a row whose strip
-        // wraps can have one. Such rows take per-column accesses; all others
-        // move a lane's columns (and, when aligned, its indices) at once.
+        // CPL divides nc (the geometry keeps nc even), no lane straddles;
+        // otherwise only a row whose strip wraps can have one. Loads decide
+        // by the row class alone, at compile time (class r = 0 mod CPL has
+        // base -a r = 0 mod CPL for every shear a), because a branch around
+        // a prefetched load makes the compiler wait for all loads where the
+        // paths join. Stores, and the index loads of one-level passes, also
+        // take the aligned form in the other classes when the row allows it.
         bool lal[4], sal[4], qal[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -282,6 +286,7 @@ struct StreamSplit {
             qal[r] = (reinterpret_cast<uintptr_t>(qbase[r]) & 3) == 0;
         }
         constexpr uint32_t STRIP_BYTES = 4u * CPL * 64u;
+        constexpr bool QLOAD_VEC = LEVELS == 1;   // measured: faster there, slower for pairs of levels
         auto load4 = [&](int u_next) __attribute__((always_inline)) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -293,7 +298,7 @@ struct StreamSplit {
                     // followed by a float load would compute
                     const int16_t* qr = qbase[r] + ro;
                     int16_t q[CPL];
-                    if (lal[r] && qal[r]) {
+                    if (QLOAD_VEC && lal[r] && qal[r]) {
                         ld_vec<CPL>(qr, colofs(cb, 0) >> 1, q);
                     } else {
 #pragma unroll
@@ -304,7 +309,7 @@ struct StreamSplit {
                 } else {
                     const float* rp = lbase[r] + ro;
                     float x[CPL];
-                    if (lal[r] || uint32_t(cb) + STRIP_BYTES <= ncb) {
+                    if (r % CPL == 0) {
                         ld_vec<CPL>(rp, colofs(cb, 0), x);
                     } else {
 #pragma unroll
