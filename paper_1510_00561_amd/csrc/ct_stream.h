@@ -257,6 +257,7 @@ struct StreamSplit {
         constexpr int SSH = ANA ? CSH : 0;
 
         Row w[RING];
+        float lastq[2][UNROLL];      // odd row classes: the last lane's second column
 #pragma unroll
         for (int r = 0; r < RING; ++r)
 #pragma unroll
@@ -287,6 +288,10 @@ struct StreamSplit {
         }
         constexpr uint32_t STRIP_BYTES = 4u * CPL * 64u;
         constexpr bool QLOAD_VEC = LEVELS == 1;   // measured: faster there, slower for pairs of levels
+        constexpr bool ODD_PAIRS = true;
+        const bool a_odd = (g.a & 1) != 0;          // odd row classes have an odd column base
+        const uint32_t odd4 = a_odd ? 4u : 0u;
+        const uint32_t c127 = 4u * uint32_t(127 % nc);   // last lane's second column, from the base
         auto load4 = [&](int u_next) __attribute__((always_inline)) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -311,17 +316,44 @@ struct StreamSplit {
                     float x[CPL];
                     if (r % CPL == 0) {
                         ld_vec<CPL>(rp, colofs(cb, 0), x);
+                    } else if (ODD_PAIRS && CPL == 2) {
+                        // odd classes: load the even-aligned pair that holds the
+                        // lane's first column, and the last lane's second column
+                        // (wave-uniform); fix_odd() arranges them when the row is
+                        // first used
+                        const uint32_t o0 = colofs(cb, 0);
+                        ld_vec<2>(rp, o0 - odd4, x);
+                        uint32_t yb = uint32_t(cb) + c127;
+                        yb = yb >= ncb ? yb - ncb : yb;
+                        lastq[r >> 1][u_next % UNROLL] = ld_at(rp, yb);
                     } else {
 #pragma unroll
                         for (int e = 0; e < CPL; ++e) x[e] = ld_at(rp, colofs(cb, e));
                     }
+                    const bool raw = ODD_PAIRS && CPL == 2 && r % CPL != 0;   // scaled in fix_odd
 #pragma unroll
-                    for (int e = 0; e < CPL; ++e) X.v[e] = lsc[r] * x[e];
+                    for (int e = 0; e < CPL; ++e) X.v[e] = raw ? x[e] : lsc[r] * x[e];
                 }
                 lrow[r] += r4;
                 lrow[r] = lrow[r] >= nr ? lrow[r] - nr : lrow[r];
                 lcb[r] -= a4b;
                 lcb[r] = lcb[r] < 0 ? lcb[r] + int(ncb) : lcb[r];
+            }
+        };
+        // odd row classes, loaded as even-aligned pairs: with an odd base the
+        // lane's columns are the pair's second element and the next lane's
+        // first element (the last lane's comes from its own load); the scale
+        // follows
+        auto fix_odd = [&](int u) __attribute__((always_inline)) {
+            if (!ODD_PAIRS || CPL != 2 || (!ANA && QUANT)) return;
+#pragma unroll
+            for (int r = 1; r < 4; r += 2) {
+                Row& X = w[slot(4 * u + r)];
+                const float nx = from_next(X.v[0]);
+                const float x0 = a_odd ? X.v[1] : X.v[0];
+                const float x1 = a_odd ? (lane == 63 ? lastq[r >> 1][u % UNROLL] : nx) : X.v[1];
+                X.v[0] = lsc[r] * x0;
+                X.v[1] = lsc[r] * x1;
             }
         };
         auto store4 = [&](int u, int n) __attribute__((always_inline)) {
@@ -375,6 +407,7 @@ struct StreamSplit {
                 // the rows of superstep u + PF go into ring slots that no step
                 // of this superstep reads (PF supersteps of latency hiding)
                 load4(u + PF);
+                fix_odd(u);
 #pragma unroll
                 for (int q = 0; q < NSTEP; ++q) apply_step<FO>(w, u, q);
                 store4(u, n0 + u);
