@@ -57,7 +57,7 @@ int launch_chain(const std::vector<StageDesc>& chain, hipStream_t st);
 int fill_quant_args(const Geometry& g, QuantArgs* a);
 int resident_waves();
 // Rows per streamed block of an LP-level stage and of a split stage.
-int level_block_rows(int Rj, int Cj, int batch);
+int level_block_rows(int Rj, int Cj, int batch, bool synthesis);
 int split_block_rows(const SplitArgs& a, int batch, int levels);
 
 // Work-queue tiles of an LP-level stage (one wavefront item per strip and
