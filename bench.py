@@ -28,13 +28,13 @@ FRAMES = 16
 PLANES = 3 * FRAMES
 
 # kernel -> sources whose text defines it (a change invalidates its counters)
-KERNEL_SOURCES = {
-    "lp_dfb12_analysis": ("ct_level.hip", "ct_stream_level.h", "ct_stream.h", "ct_kernels.h"),
-    "dfb12_lp_synthesis": ("ct_level.hip", "ct_stream_level.h", "ct_stream.h", "ct_kernels.h"),
-    "dfb_split_analysis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h"),
-    "dfb_split_synthesis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h"),
-    "dfb_split2_analysis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h"),
-    "dfb_split2_synthesis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h"),
+KERNEL_SOURCES = {   # the kernel's code and the host code that sets its launch shape (block heights)
+    "lp_dfb12_analysis": ("ct_level.hip", "ct_stream_level.h", "ct_stream.h", "ct_kernels.h", "ct_api.cpp"),
+    "dfb12_lp_synthesis": ("ct_level.hip", "ct_stream_level.h", "ct_stream.h", "ct_kernels.h", "ct_api.cpp"),
+    "dfb_split_analysis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h", "ct_api.cpp"),
+    "dfb_split_synthesis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h", "ct_api.cpp"),
+    "dfb_split2_analysis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h", "ct_api.cpp"),
+    "dfb_split2_synthesis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h", "ct_api.cpp"),
     "pad_fold": ("ct_level.hip",),
     "lowpass_partial": ("ct_quant.hip", "ct_quant_stages.h"),
     "quantize": ("ct_quant.hip", "ct_quant_stages.h"),
