@@ -268,27 +268,31 @@ struct StreamSplit {
             const uint32_t o = uint32_t(cb) + m[e];
             return min(o, o - ncb);
         };
-        // A lane's CPL columns are consecutive in memory unless they straddle
-        // the end of the row. Row class r has a fixed column base modulo CPL
-        // (its base moves by 4 a columns per superstep): when that is 0 and
-        // CPL divides nc (the geometry keeps nc even), no lane straddles;
-        // otherwise only a row whose strip wraps can have one. Loads decide
-        // by the row class alone, at compile time (class r = 0 mod CPL has
-        // base -a r = 0 mod CPL for every shear a), because a branch around
-        // a prefetched load makes the compiler wait for all loads where the
-        // paths join. Stores, and the index loads of one-level passes, also
-        // take the aligned form in the other classes when the row allows it.
+        // A lane's two columns are consecutive in memory unless they straddle
+        // the end of the row. Row class r has a fixed column base modulo 2
+        // (its base moves by 4 a columns per superstep, and the geometry keeps
+        // nc even): even classes are always even-aligned, odd classes are when
+        // the shear a is even. Loads decide by the class alone, at compile
+        // time, because a branch around a prefetched load makes the compiler
+        // wait for all loads where the paths join:
+        //   even classes load the lane's pair;
+        //   odd classes load the even-aligned pair holding the lane's first
+        //   column and, with an odd shear, take the second column from the
+        //   next lane (fix_odd, at the row's first use) and the last lane's
+        //   from one wave-uniform load.
+        // Stores branch on the row: the pair at once unless it straddles the
+        // row end; the index loads of one-level passes likewise.
+        static_assert(CPL == 2, "the pair forms below assume two columns per lane");
         bool lal[4], sal[4], qal[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            lal[r] = nc % CPL == 0 && (lcb[r] >> 2) % CPL == 0;
-            sal[r] = nc % CPL == 0 && (scb[r] >> 2) % CPL == 0;
+            lal[r] = (lcb[r] >> 2) % CPL == 0;
+            sal[r] = (scb[r] >> 2) % CPL == 0;
             // indices move CPL at once only from dword-aligned addresses
             qal[r] = (reinterpret_cast<uintptr_t>(qbase[r]) & 3) == 0;
         }
         constexpr uint32_t STRIP_BYTES = 4u * CPL * 64u;
         constexpr bool QLOAD_VEC = LEVELS == 1;   // measured: faster there, slower for pairs of levels
-        constexpr bool ODD_PAIRS = true;
         const bool a_odd = (g.a & 1) != 0;          // odd row classes have an odd column base
         const uint32_t odd4 = a_odd ? 4u : 0u;
         const uint32_t c127 = 4u * uint32_t(127 % nc);   // last lane's second column, from the base
@@ -311,28 +315,21 @@ struct StreamSplit {
                     }
 #pragma unroll
                     for (int e = 0; e < CPL; ++e) X.v[e] = lsc[r] * __fmul_rn(float(q[e]), qstep[r]);
+                } else if (r % 2 == 0) {
+                    float x[CPL];
+                    ld_vec<CPL>(lbase[r] + ro, colofs(cb, 0), x);
+#pragma unroll
+                    for (int e = 0; e < CPL; ++e) X.v[e] = lsc[r] * x[e];
                 } else {
+                    // raw values; fix_odd arranges and scales them
                     const float* rp = lbase[r] + ro;
                     float x[CPL];
-                    if (r % CPL == 0) {
-                        ld_vec<CPL>(rp, colofs(cb, 0), x);
-                    } else if (ODD_PAIRS && CPL == 2) {
-                        // odd classes: load the even-aligned pair that holds the
-                        // lane's first column, and the last lane's second column
-                        // (wave-uniform); fix_odd() arranges them when the row is
-                        // first used
-                        const uint32_t o0 = colofs(cb, 0);
-                        ld_vec<2>(rp, o0 - odd4, x);
-                        uint32_t yb = uint32_t(cb) + c127;
-                        yb = yb >= ncb ? yb - ncb : yb;
-                        lastq[r >> 1][u_next % UNROLL] = ld_at(rp, yb);
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < CPL; ++e) x[e] = ld_at(rp, colofs(cb, e));
-                    }
-                    const bool raw = ODD_PAIRS && CPL == 2 && r % CPL != 0;   // scaled in fix_odd
-#pragma unroll
-                    for (int e = 0; e < CPL; ++e) X.v[e] = raw ? x[e] : lsc[r] * x[e];
+                    ld_vec<CPL>(rp, colofs(cb, 0) - odd4, x);
+                    X.v[0] = x[0];
+                    X.v[1] = x[1];
+                    uint32_t yb = uint32_t(cb) + c127;
+                    yb = yb >= ncb ? yb - ncb : yb;
+                    lastq[r >> 1][u_next % UNROLL] = ld_at(rp, yb);
                 }
                 lrow[r] += r4;
                 lrow[r] = lrow[r] >= nr ? lrow[r] - nr : lrow[r];
@@ -345,7 +342,7 @@ struct StreamSplit {
         // first element (the last lane's comes from its own load); the scale
         // follows
         auto fix_odd = [&](int u) __attribute__((always_inline)) {
-            if (!ODD_PAIRS || CPL != 2 || (!ANA && QUANT)) return;
+            if (!ANA && QUANT) return;
 #pragma unroll
             for (int r = 1; r < 4; r += 2) {
                 Row& X = w[slot(4 * u + r)];
