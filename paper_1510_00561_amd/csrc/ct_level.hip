@@ -1,7 +1,6 @@
 // Per-stage kernels for gfx950: the fused LP level + DFB tree levels 1-2
-// (analysis and synthesis, persistent), the deeper DFB tree levels one or
-// two at a time (register streaming), and the transpose of the mirror
-// padding.
+// (analysis and synthesis), the deeper DFB tree levels one or two at a time,
+// all register-streaming, and the transpose of the mirror padding.
 //
 // Paper section 2.1 (LP, then a DFB on each bandpass image, 9-7 filters),
 // section 3.3 (half resolution per level), section 3.10 (periodic, FFT-style
