@@ -41,7 +41,11 @@ struct GroupSmem {
 };
 
 template <int TYPE>
-__global__ __launch_bounds__(NT) void group_kernel(const StageDesc* stages, const int* first, int n) {
+// The descriptor table is read-only for the whole launch (__restrict__), so
+// the compiler may keep a stage's arguments in registers across its stores
+// instead of loading them again after each one.
+__global__ __launch_bounds__(NT) void group_kernel(const StageDesc* __restrict__ stages,
+                                                   const int* __restrict__ first, int n) {
     __shared__ float smem[GroupSmem<TYPE>::value];
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int s = find_stage(first, n, t);
