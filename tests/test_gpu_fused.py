@@ -29,6 +29,9 @@ CASES = [
     ("mixed", 64, 96, 2, [4, 32], 2),
     ("deep6", 192, 256, 6, [8, 8, 4, 4, 4, 4], 1),
     ("c3", 1080, 1920, 4, [32, 16, 8, 8], 3),
+    ("oddlow", 40, 40, 3, [8, 4, 4], 3),
+    ("min8", 4, 4, 1, [8], 2),
+    ("wide", 24, 200, 2, [16, 4], 2),
 ]
 
 

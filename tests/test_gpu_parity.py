@@ -51,6 +51,15 @@ CASES = [
     ("mixed", 64, 96, 2, [4, 32], 2),
     ("deep6", 192, 256, 6, [8, 8, 4, 4, 4, 4], 1),
     ("c5", 720, 1280, 3, [16, 8, 4], 1),
+    # odd coefficient count (5x5 lowpass): every other plane's indices start
+    # at an odd element
+    ("oddlow", 40, 40, 3, [8, 4, 4], 3),
+    # smallest frames: a one-level split of 2-row parents, a two-level split
+    # of 4x4 parents
+    ("min8", 4, 4, 1, [8], 2),
+    ("min16", 8, 8, 1, [16], 2),
+    # channels narrower than a strip, rows wider than two strips
+    ("wide", 24, 200, 2, [16, 4], 2),
 ]
 
 
@@ -81,7 +90,10 @@ def test_forward_inverse_parity(name, H, W, J, dirs, B):
         assert np.abs(rec2[b] - want).max() <= TOL
 
 
-@pytest.mark.parametrize("name,H,W,J,dirs,B", CASES[:5], ids=[c[0] for c in CASES[:5]])
+QCASES = CASES[:5] + [c for c in CASES if c[0] in ("oddlow", "min8", "wide")]
+
+
+@pytest.mark.parametrize("name,H,W,J,dirs,B", QCASES, ids=[c[0] for c in QCASES])
 def test_quantiser_bit_exact(name, H, W, J, dirs, B):
     _show(name, H=H, W=W, J=J, dirs=dirs, B=B)
     x = _frames(name, H, W, B)
@@ -151,8 +163,10 @@ def test_quantise_gpu_coefficients_mismatch_rate():
     assert np.abs(q.astype(int) - q_ref).max() <= 1
 
 
-@pytest.mark.parametrize("name,H,W,J,dirs,B", [CASES[0], CASES[2], CASES[5], CASES[6]],
-                         ids=["c1", "ragged", "mixed", "deep6"])
+ACASES = [c for c in CASES if c[0] in ("c1", "ragged", "mixed", "deep6", "oddlow", "min8", "wide")]
+
+
+@pytest.mark.parametrize("name,H,W,J,dirs,B", ACASES, ids=[c[0] for c in ACASES])
 def test_adjoint_parity(name, H, W, J, dirs, B):
     _show(name, H=H, W=W, J=J, dirs=dirs, B=B)
     rng = np.random.default_rng(11)
