@@ -28,6 +28,8 @@ STREAMS = [
     (70, 90, 3, [16, 8, 4], 2),
     (64, 96, 2, [4, 32], 1),
     (256, 256, 2, [8, 4], 1),
+    (40, 40, 3, [8, 4, 4], 3),      # odd coefficient count
+    (4, 4, 1, [8], 2),              # smallest frame
 ]
 
 
