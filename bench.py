@@ -1,14 +1,17 @@
 """Benchmark: contourlet forward + quantise + dequantise + inverse on 1080p frames.
 
-One step is the whole hot path on one batch: 16 synthetic 1920x1080 frames
-converted to YCoCg (48 float32 planes, padded to 1088 x 1920), LP 4 levels,
+One step is the whole hot path on one batch: 16 synthetic 1920x1080 RGB
+frames, converted to YCoCg by the library beforehand (48 float32 planes: Y,
+Co + 127, Cg + 127, padded to 1088 x 1920), LP 4 levels,
 DFB 32/16/8/8 directions, per-subband quantisation steps drawn per channel
 from 4..64. Inputs are resident in HBM before timing starts.
 
 Prints one JSON line. `value` is frames/s (real 1080p frames). The line also
 carries the effective HBM bandwidth of the step (algorithmic bytes / time),
-the roofline of the dominant kernel from live per-launch HIP events, and the
-FP64 oracle timed on the host cores on a bounded sample.
+the roofline of the dominant kernel from live per-launch HIP events, the
+colour front end / back end and K-frame lowpass filter measured on the same
+frames (outside the step), and the FP64 oracle timed on the host cores on a
+bounded sample.
 """
 import argparse
 import hashlib
@@ -68,13 +71,15 @@ def measured_traffic(name, bytes_per_launch):
     return ent.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(planes_np, steps_np, seconds_budget=30.0):
+def cpu_baseline(rgb_frame, steps_np, seconds_budget=30.0):
     """The FP64 oracle on one 1080p YCoCg frame (3 planes), single process."""
     import numpy as np
+    from oracle import color
     from oracle import ct as oct
     from oracle import geometry as geo
     from oracle import quant as oq
     table = geo.subband_table(H, W, J, DIRS)
+    planes_np = np.stack(color.encode_frame(rgb_frame, 1))
     t0 = time.perf_counter()
     n = 0
     for b in range(3):
@@ -93,6 +98,50 @@ def cpu_baseline(planes_np, steps_np, seconds_budget=30.0):
                       f"in FP64 NumPy, one process ({dt:.1f} s)"}
 
 
+def ycocg_planes(rgb):
+    """[B, H, W, 3] uint8 device frames -> [3B, H, W] float32 planes Y, Co + 127,
+    Cg + 127 of each frame in turn (the library's colour stage, chroma factor 1)."""
+    import torch
+    from paper_1510_00561_amd import ct
+    y, co, cg = ct.rgb_to_ycocg(rgb, 1)
+    B, Hh, Ww = y.shape
+    return torch.stack([y, co, cg], dim=1).reshape(3 * B, Hh, Ww).contiguous()
+
+
+def front_back_stages(rgb, plan, idx, steps, n=4):
+    """Colour front end and back end on the bench's frames (chroma factor n),
+    and the K-frame lowpass filter and its inverse on the step's indices:
+    per-kernel time from HIP events, achieved against HBM peak."""
+    import torch
+    from paper_1510_00561_amd import ct
+    y, co, cg = ct.rgb_to_ycocg(rgb, n)
+    out = ct.ycocg_to_rgb(y, co, cg, n)
+    work = idx.clone()
+    torch.cuda.synchronize()
+    ct.profile_enable(True, 8192)
+    for _ in range(steps):
+        ct.rgb_to_ycocg(rgb, n, y, co, cg)
+        ct.ycocg_to_rgb(y, co, cg, n, out)
+        plan.lowpass_diff(work)
+        plan.lowpass_diff(work, inverse=True)
+    torch.cuda.synchronize()
+    stats = ct.profile_collect()
+    ct.profile_enable(False)
+    restored = bool(torch.equal(work, idx))
+    y1, co1, cg1 = ct.rgb_to_ycocg(rgb, 1)
+    exact = bool(torch.equal(ct.ycocg_to_rgb(y1, co1, cg1, 1), rgb.float()))
+    kern = {}
+    for name, (cnt, tms, by) in stats.items():
+        gbps = by / (tms / 1e3) / 1e9
+        kern[name] = {"avg_launch_us": round(tms / cnt * 1e3, 2), "bytes_per_launch": by / cnt,
+                      "achieved_gbps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4)}
+    B, Hh, Ww, _ = rgb.shape
+    return {"workload": f"{B} x {Ww}x{Hh} RGB frames, chroma factor {n}; K-frame lowpass filter and its "
+                        f"inverse on the step's {idx.shape[0]} planes of indices",
+            "bound": "hbm", "peak_gbps": HBM_PEAK_GBPS, "kernels": kern,
+            "lowpass_roundtrip_exact": restored, "colour_roundtrip_exact_factor1": exact}
+
+
 def batched_comparison(steps):
     """Mixed workload: 64 streams (one YCoCg frame each) of 320x240, 640x480 or
     1280x720, LP depth 2-4, 8-16 directions, as one graph launch of grouped
@@ -103,12 +152,12 @@ def batched_comparison(steps):
     streams = synth.mixed_streams(64, 4)
     clips = {}
     for (h, w) in sorted({(s[0], s[1]) for s in streams}):
-        clips[(h, w)] = synth.clip_planes(8, h, w, 4)
+        clips[(h, w)] = ycocg_planes(torch.from_numpy(synth.clip_rgb(8, h, w, 4)).cuda())
     rng = synth.rng_for(4)
     descs = []
     for i, (h, w, J, dirs) in enumerate(streams):
         fr = i % 8
-        planes = torch.from_numpy(np.ascontiguousarray(clips[(h, w)][3 * fr:3 * fr + 3])).cuda()
+        planes = clips[(h, w)][3 * fr:3 * fr + 3].contiguous()
         nsub = int(ct.layout(h, w, J, dirs)[0].nsub)
         step_table = torch.from_numpy(rng.integers(4, 65, size=(3, nsub)).astype(np.float32)).cuda()
         descs.append(dict(height=h, width=w, levels=J, dirs=dirs, planes=planes, steps=step_table))
@@ -176,13 +225,14 @@ def main():
         return
 
     print(f"[bench] generating {FRAMES} frames of {W}x{H}", file=sys.stderr, flush=True)
-    planes_np = synth.clip_planes(FRAMES, H, W, 3)
+    rgb_np = synth.clip_rgb(FRAMES, H, W, 3)
     plan = ct.Plan(H, W, J, DIRS, PLANES, "cuda:0")
     steps_tab = synth.subband_steps(plan.nsub, 3, 3)            # [3][nsub]
     steps_np = np.stack([steps_tab[b % 3] for b in range(PLANES)]).astype(np.float32)
 
     dev = torch.device("cuda:0")
-    x = torch.from_numpy(planes_np).to(dev)
+    rgb = torch.from_numpy(rgb_np).to(dev)
+    x = ycocg_planes(rgb)
     steps = torch.from_numpy(steps_np).to(dev)
     coef = torch.empty((PLANES, plan.ncoef), dtype=torch.float32, device=dev)
     coef2 = torch.empty_like(coef)
@@ -263,10 +313,13 @@ def main():
         print("[bench] batched mixed-stream comparison", file=sys.stderr, flush=True)
         batched = batched_comparison(max(3, args.steps // 2))
 
+    print("[bench] colour and K-frame stages", file=sys.stderr, flush=True)
+    fb = front_back_stages(rgb, plan, idx, max(3, args.steps // 2))
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(planes_np, steps_tab)
+        cpu = cpu_baseline(rgb_np[0], steps_tab)
 
     out = {
         "metric": METRIC, "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1,
@@ -288,6 +341,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "batched": batched,
+        "front_back": fb,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -263,6 +263,55 @@ int ct_plan_info(const ct_plan* plan, ct_plan_info_t* info);
 void ct_plan_destroy(ct_plan* plan);
 
 /*
+ * Encoder front end and decoder back end (paper section 2.3, Table I;
+ * section 3.1). These calls take sizes instead of a ct_geom; they follow the
+ * other conventions above (device pointers owned by the caller, enqueue only,
+ * validation before any launch, CT_ERR_* returns) and need no workspace.
+ *   batch, height, width  B frames of H x W pixels (B >= 0, H, W >= 1), with
+ *                         3 * B * H * W < 2^31, else CT_ERR_ARG.
+ *   n                     chroma subsampling factor, 1..CT_MAX_CHROMA_FACTOR
+ *                         (1 keeps every sample). Chroma planes are
+ *                         Hc x Wc with Hc = ceil(H / n), Wc = ceil(W / n).
+ *   rgb (forward)         uint8 [B][H][W][3], R, G, B interleaved, 4-byte
+ *                         aligned.
+ *   y                     float32 [B][H][W] luminance planes, 16-byte
+ *                         aligned: the layout ct_forward / ct_encode take.
+ *   co, cg                float32 [B][Hc][Wc] chroma planes.
+ * ct_rgb_to_ycocg applies equations (1)-(3) to every pixel, writes Y, and
+ * writes Co + 127 and Cg + 127 at the samples (n i, n j) (section 3.1: chroma
+ * kept at every n-th row and column and moved into [0, 255] by +127; exactly,
+ * equations (2)-(3) reach +-127.5, so values lie in [-0.5, 254.5]). Every
+ * result is exact in float32 (quarter integers below 2^10).
+ * ct_ycocg_to_rgb is the decoder side: for pixel (r, c) it interpolates each
+ * chroma plane bilinearly between samples floor(r / n), floor(c / n) and the
+ * next ones (the last sample repeated past the edge) with weights
+ * (r mod n) / n and (c mod n) / n, subtracts 127, and applies equations
+ * (4)-(6). Output rgb float32 [B][H][W][3] interleaved, 16-byte aligned,
+ * neither rounded nor clamped. float32 arithmetic, weights from 1/n rounded
+ * to float32.
+ */
+#define CT_MAX_CHROMA_FACTOR 64
+int ct_rgb_to_ycocg(int32_t batch, int32_t height, int32_t width, int32_t n, const uint8_t* rgb,
+                    float* y, float* co, float* cg, hipStream_t stream);
+int ct_ycocg_to_rgb(int32_t batch, int32_t height, int32_t width, int32_t n, const float* y,
+                    const float* co, const float* cg, float* rgb, hipStream_t stream);
+
+/*
+ * K-frame lowpass filtering (paper section 3.7), in place on the int16
+ * indices of ct_quantize / ct_encode (idx [batch][ncoef], batch * ncoef <
+ * 2^31). Only each plane's lowpass (subband 0: rows x cols at offset 0, row
+ * major) changes.
+ *   inverse = 0  every element below the first row becomes its difference
+ *                with the element above it in the input;
+ *   inverse != 0 the running sums down every column, undoing the above.
+ * Differences and sums wrap modulo 2^16 (two's complement int16), so the
+ * pair restores any input exactly; for the quantiser's lowpass indices
+ * (0..255) no wrap occurs and the differences are the exact ones.
+ */
+int ct_lowpass_diff(const ct_geom* geom, int32_t batch, int16_t* idx, int32_t inverse,
+                    hipStream_t stream);
+
+/*
  * Per-kernel timing (HIP events), for benchmarks and tracing.
  * ct_profile_enable(1) creates a pool of `max_launches` event pairs (0 picks
  * 16384) and makes every later launch record one event before and one after

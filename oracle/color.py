@@ -56,23 +56,28 @@ def subsample(c, n):
     return c[::n, ::n] + CHROMA_OFFSET
 
 
-def upsample(cs, n, height, width):
-    """Section 3.1, decoder: bilinear interpolation of the kept samples to a
-    height x width plane, then the 127 offset removed. Written per pixel."""
-    cs = np.asarray(cs, dtype=np.float64)
+def upsample_pixel(cs, n, yy, xx):
+    """Section 3.1, decoder: the chroma value at pixel (yy, xx), bilinear
+    between the four kept samples around it, with the 127 offset removed."""
     hs, ws = cs.shape
+    i0 = yy // n
+    fy = (yy - n * i0) / n
+    i1 = min(i0 + 1, hs - 1)
+    j0 = xx // n
+    fx = (xx - n * j0) / n
+    j1 = min(j0 + 1, ws - 1)
+    v = ((1 - fy) * ((1 - fx) * float(cs[i0, j0]) + fx * float(cs[i0, j1]))
+         + fy * ((1 - fx) * float(cs[i1, j0]) + fx * float(cs[i1, j1])))
+    return v - CHROMA_OFFSET
+
+
+def upsample(cs, n, height, width):
+    """upsample_pixel over a height x width plane."""
+    cs = np.asarray(cs, dtype=np.float64)
     out = np.empty((height, width))
     for yy in range(height):
-        i0 = yy // n
-        fy = (yy - n * i0) / n
-        i1 = min(i0 + 1, hs - 1)
         for xx in range(width):
-            j0 = xx // n
-            fx = (xx - n * j0) / n
-            j1 = min(j0 + 1, ws - 1)
-            v = ((1 - fy) * ((1 - fx) * cs[i0, j0] + fx * cs[i0, j1])
-                 + fy * ((1 - fx) * cs[i1, j0] + fx * cs[i1, j1]))
-            out[yy, xx] = v - CHROMA_OFFSET
+            out[yy, xx] = upsample_pixel(cs, n, yy, xx)
     return out
 
 

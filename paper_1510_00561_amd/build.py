@@ -24,6 +24,8 @@ SOURCES = [
     ("ct_level.hip", ["-ffp-contract=off"]),
     ("ct_quant.hip", ["-ffp-contract=off"]),
     ("ct_batched.hip", ["-ffp-contract=off"]),
+    ("ct_color_api.cpp", []),
+    ("ct_color.hip", ["-ffp-contract=off"]),
 ]
 
 COMMON = [

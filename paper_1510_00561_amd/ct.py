@@ -6,7 +6,8 @@ workspace, and checks return codes. There is no fallback: if the library is
 missing or a call fails, an exception is raised.
 
 Names follow the C ABI (include/ct.h): forward, inverse, quantize,
-dequantize, forward_adjoint, inverse_adjoint, layout.
+dequantize, forward_adjoint, inverse_adjoint, layout, rgb_to_ycocg,
+ycocg_to_rgb, lowpass_diff.
 """
 import ctypes
 import os
@@ -97,6 +98,9 @@ def _lib():
             "ct_dequantize": [G, i32, P, P, i32, P, P, P],
             "ct_encode": [G, i32, P, P, i32, P, P, P, P, sz, P],
             "ct_decode": [G, i32, P, P, i32, P, P, P, sz, P],
+            "ct_rgb_to_ycocg": [i32, i32, i32, i32, P, P, P, P, P],
+            "ct_ycocg_to_rgb": [i32, i32, i32, i32, P, P, P, P, P],
+            "ct_lowpass_diff": [G, i32, P, i32, P],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -259,6 +263,14 @@ class Plan:
         _check("ct_dequantize", rc)
         return out
 
+    def lowpass_diff(self, idx, inverse=False):
+        """K-frame lowpass filtering of idx [B, ncoef] int16 in place (ct_lowpass_diff)."""
+        self._check_tensor(idx, (self.batch, self.ncoef), torch.int16, "idx")
+        rc = _lib().ct_lowpass_diff(ctypes.byref(self.g), self.batch, ctypes.c_void_p(idx.data_ptr()),
+                                    1 if inverse else 0, self._stream())
+        _check("ct_lowpass_diff", rc)
+        return idx
+
     def encode(self, x, steps, idx=None, side=None, coeffs=None):
         """Fused forward CT + quantise: (idx [B, ncoef] int16, side [B, 2]);
         `coeffs` (optional [B, ncoef] float32) also receives the coefficients."""
@@ -308,6 +320,65 @@ def forward(x, levels, dirs):
 def inverse(coeffs, height, width, levels, dirs):
     B = coeffs.shape[0]
     return Plan(height, width, levels, dirs, B, coeffs.device).inverse(coeffs.contiguous())
+
+
+def _cuda(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def chroma_shape(height, width, n):
+    """(ceil(H / n), ceil(W / n)); the library checks the range of n."""
+    if int(n) < 1:
+        raise ValueError(f"chroma factor must be >= 1, got {n}")
+    return -(-int(height) // int(n)), -(-int(width) // int(n))
+
+
+def rgb_to_ycocg(rgb, n, y=None, co=None, cg=None):
+    """uint8 RGB [B, H, W, 3] -> (Y [B, H, W], Co + 127, Cg + 127 [B, Hc, Wc]) float32."""
+    if rgb.dim() != 4 or rgb.shape[-1] != 3:
+        raise ValueError("rgb must be [B, H, W, 3]")
+    B, H, W, _ = rgb.shape
+    Hc, Wc = chroma_shape(H, W, n)
+    _cuda(rgb, torch.uint8, (B, H, W, 3), "rgb")
+    dev = rgb.device
+    y = torch.empty((B, H, W), dtype=torch.float32, device=dev) if y is None else y
+    co = torch.empty((B, Hc, Wc), dtype=torch.float32, device=dev) if co is None else co
+    cg = torch.empty((B, Hc, Wc), dtype=torch.float32, device=dev) if cg is None else cg
+    _cuda(y, torch.float32, (B, H, W), "y")
+    _cuda(co, torch.float32, (B, Hc, Wc), "co")
+    _cuda(cg, torch.float32, (B, Hc, Wc), "cg")
+    st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    rc = _lib().ct_rgb_to_ycocg(B, H, W, int(n), ctypes.c_void_p(rgb.data_ptr()),
+                                ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(co.data_ptr()),
+                                ctypes.c_void_p(cg.data_ptr()), st)
+    _check("ct_rgb_to_ycocg", rc)
+    return y, co, cg
+
+
+def ycocg_to_rgb(y, co, cg, n, out=None):
+    """(Y [B, H, W], Co + 127, Cg + 127 [B, Hc, Wc]) -> float32 RGB [B, H, W, 3]."""
+    if y.dim() != 3:
+        raise ValueError("y must be [B, H, W]")
+    B, H, W = y.shape
+    Hc, Wc = chroma_shape(H, W, n)
+    _cuda(y, torch.float32, (B, H, W), "y")
+    _cuda(co, torch.float32, (B, Hc, Wc), "co")
+    _cuda(cg, torch.float32, (B, Hc, Wc), "cg")
+    out = torch.empty((B, H, W, 3), dtype=torch.float32, device=y.device) if out is None else out
+    _cuda(out, torch.float32, (B, H, W, 3), "rgb")
+    st = ctypes.c_void_p(torch.cuda.current_stream(y.device).cuda_stream)
+    rc = _lib().ct_ycocg_to_rgb(B, H, W, int(n), ctypes.c_void_p(y.data_ptr()),
+                                ctypes.c_void_p(co.data_ptr()), ctypes.c_void_p(cg.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr()), st)
+    _check("ct_ycocg_to_rgb", rc)
+    return out
 
 
 class Batched:

@@ -5,9 +5,10 @@ frame (section 4); neither is available here. These generators stand in for
 them with the same kind of content: a static textured background, moving
 objects with sharp edges, and sensor noise, on 8-bit RGB or luma frames.
 
-This module holds only input synthesis (NumPy, no transform arithmetic).
-The RGB -> YCoCg conversion of Table 1 is applied here as input
-preparation: the contourlet transform runs on the Y, Co, Cg planes.
+This module holds only input synthesis (NumPy, none of the method's
+arithmetic): frames come out as 8-bit RGB; the conversion to the Y, Co, Cg
+planes the contourlet transform runs on is the library's (or, in tests,
+the oracle's).
 Random draws use numpy's default_rng with seed 1510_00561 + workload number.
 """
 import numpy as np
@@ -95,21 +96,10 @@ class ClipGenerator:
         return np.clip(np.rint(img), 0, 255).astype(np.uint8)
 
 
-def rgb_to_ycocg(rgb):
-    """Table 1, equations (1)-(3): Y, Co, Cg planes as float32 (exact: quarter integers)."""
-    x = rgb.astype(np.float32)
-    R, G, B = x[..., 0], x[..., 1], x[..., 2]
-    Y = R / 4 + G / 2 + B / 4
-    Co = R / 2 - B / 2
-    Cg = -R / 4 + G / 2 - B / 4
-    return np.stack([Y, Co, Cg]).astype(np.float32)
-
-
-def clip_planes(n_frames, height, width, workload):
-    """[n_frames * 3, height, width] float32 YCoCg planes of a synthetic clip."""
+def clip_rgb(n_frames, height, width, workload):
+    """[n_frames, height, width, 3] uint8 RGB frames of a synthetic clip."""
     gen = ClipGenerator(height, width, SEED_BASE + workload)
-    planes = [rgb_to_ycocg(gen.frame(t)) for t in range(n_frames)]
-    return np.concatenate(planes, axis=0)
+    return np.stack([gen.frame(t) for t in range(n_frames)])
 
 
 def subband_steps(nsub, n_channels=3, workload=3, low=4, high=64):

@@ -113,6 +113,9 @@ def test_fault_injection_hook(ct, monkeypatch):
     monkeypatch.setenv("CT_FAULT_INJECT", "launch")
     assert lib.ct_forward(ctypes.byref(g), 1, dummy, dummy, dummy, need, None) == -4
     assert lib.ct_quantize(ctypes.byref(g), 1, dummy, dummy, 0, dummy, dummy, dummy, need, None) == -4
+    assert lib.ct_rgb_to_ycocg(1, 4, 4, 2, dummy, dummy, dummy, dummy, None) == -4
+    assert lib.ct_ycocg_to_rgb(1, 4, 4, 2, dummy, dummy, dummy, dummy, None) == -4
+    assert lib.ct_lowpass_diff(ctypes.byref(g), 1, dummy, 1, None) == -4
     assert lib.ct_strerror(-4) == b"HIP runtime error"
 
 
@@ -145,3 +148,29 @@ def test_plan_validation_errors(ct):
     info = ct.PlanInfo()
     assert lib.ct_plan_info(None, ctypes.byref(info)) == -1
     lib.ct_plan_destroy(None)
+
+
+def test_colour_and_lowpass_validation(ct):
+    # every error path returns before any launch, so this runs without a GPU
+    lib = ct._lib()
+    d4 = ctypes.c_void_p(0x1000)       # 16-byte aligned dummies
+    odd = ctypes.c_void_p(0x1004)      # 4-byte but not 16-byte aligned
+    for fn in ("ct_rgb_to_ycocg", "ct_ycocg_to_rgb"):
+        f = getattr(lib, fn)
+        assert f(0, 4, 4, 2, None, None, None, None, None) == 0          # empty batch
+        assert f(1, 4, 4, 0, d4, d4, d4, d4, None) == -1                 # n < 1
+        assert f(1, 4, 4, 65, d4, d4, d4, d4, None) == -1                # n > maximum
+        assert f(-1, 4, 4, 1, d4, d4, d4, d4, None) == -1
+        assert f(1, 0, 4, 1, d4, d4, d4, d4, None) == -1
+        assert f(1, 4, 4, 1, d4, d4, None, d4, None) == -1               # null plane
+        assert f(1 << 10, 1 << 10, 1 << 10, 1, d4, d4, d4, d4, None) == -1   # 2^31 elements
+    assert lib.ct_rgb_to_ycocg(1, 4, 4, 1, d4, odd, d4, d4, None) == -1  # Y not 16-byte aligned
+    assert lib.ct_rgb_to_ycocg(1, 4, 4, 1, ctypes.c_void_p(0x1002), d4, d4, d4, None) == -1
+    assert lib.ct_ycocg_to_rgb(1, 4, 4, 1, d4, d4, d4, odd, None) == -1  # RGB not 16-byte aligned
+    g = ct.geom(256, 256, 2, [8, 4])
+    assert lib.ct_lowpass_diff(None, 1, d4, 0, None) == -1
+    assert lib.ct_lowpass_diff(ctypes.byref(g), 1, None, 0, None) == -1
+    assert lib.ct_lowpass_diff(ctypes.byref(g), -1, d4, 0, None) == -1
+    assert lib.ct_lowpass_diff(ctypes.byref(g), 0, None, 0, None) == 0
+    bad = ct.geom(256, 256, 2, [8, 6])
+    assert lib.ct_lowpass_diff(ctypes.byref(bad), 1, d4, 0, None) == -2

@@ -14,6 +14,7 @@ from oracle import ct as oct
 from oracle import geometry as geo
 from oracle import matrix
 from paper_1510_00561_amd import synth
+from tests import clips
 
 pytestmark = pytest.mark.gpu
 
@@ -65,7 +66,7 @@ def test_dot_products_full_size():
 def test_loss_gradient_matches_central_differences():
     """Gradient of ||S c - x||^2 + lambda ||c||_1 (ST surrogate) vs central FD, h = 1e-3."""
     from paper_1510_00561_amd import autograd as ag
-    x = np.ascontiguousarray(synth.clip_planes(B5, H5, W5, 5)[0::3])   # the 8 Y planes
+    x = np.ascontiguousarray(clips.clip_planes(B5, H5, W5, 5)[0::3])   # the 8 Y planes
     plan = _plan(H5, W5, J5, D5, B5)
     rng = np.random.default_rng(43)
     c_dev = plan.forward(_dev(x)) + 2.0 * torch.from_numpy(

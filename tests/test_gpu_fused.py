@@ -16,7 +16,7 @@ import torch
 from oracle import ct as oct
 from oracle import geometry as geo
 from oracle import quant as oq
-from paper_1510_00561_amd import synth
+from tests import clips
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +37,7 @@ CASES = [
 
 def _frames(name, H, W, B):
     if name in ("c2", "c3"):
-        return synth.clip_planes(max(1, B // 3), H, W, {"c2": 2, "c3": 3}[name])[:B]
+        return clips.clip_planes(max(1, B // 3), H, W, {"c2": 2, "c3": 3}[name])[:B]
     rng = np.random.default_rng(zlib.crc32(name.encode()))
     return rng.uniform(0, 255, (B, H, W)).astype(np.float32)
 

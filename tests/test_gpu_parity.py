@@ -16,6 +16,7 @@ from oracle import ct as oct
 from oracle import geometry as geo
 from oracle import quant as oq
 from paper_1510_00561_amd import synth
+from tests import clips
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +38,7 @@ def _frames(name, H, W, B):
         return synth.luma_edges(H, W)[None].astype(np.float32)
     if name in ("c2", "c3", "c5"):
         n_frames = max(1, B // 3)
-        planes = synth.clip_planes(n_frames, H, W, {"c2": 2, "c3": 3, "c5": 5}[name])
+        planes = clips.clip_planes(n_frames, H, W, {"c2": 2, "c3": 3, "c5": 5}[name])
         return planes[:B]
     return rng.uniform(0, 255, (B, H, W)).astype(np.float32)
 
@@ -206,7 +207,7 @@ def test_full_1080p_batch_sampled_planes():
     """
     H, W, J, dirs, B = 1080, 1920, 4, [32, 16, 8, 8], 48
     _show("c3-full", H=H, W=W, J=J, dirs=dirs, B=B)
-    x = synth.clip_planes(B // 3, H, W, 3)
+    x = clips.clip_planes(B // 3, H, W, 3)
     plan = _plan(H, W, J, dirs, B)
     xd = _dev(x)
     coef = plan.forward(xd)
