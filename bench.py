@@ -42,6 +42,10 @@ KERNEL_SOURCES = {   # the kernel's code and the host code that sets its launch 
     "lowpass_partial": ("ct_quant.hip", "ct_quant_stages.h"),
     "quantize": ("ct_quant.hip", "ct_quant_stages.h"),
     "dequantize": ("ct_quant.hip", "ct_quant_stages.h"),
+    "rgb_to_ycocg": ("ct_color.hip", "ct_color_stages.h", "ct_color_api.cpp"),
+    "ycocg_to_rgb": ("ct_color.hip", "ct_color_stages.h", "ct_color_api.cpp"),
+    "lowpass_diff": ("ct_color.hip", "ct_color_stages.h", "ct_color_api.cpp"),
+    "lowpass_undiff": ("ct_color.hip", "ct_color_stages.h", "ct_color_api.cpp"),
 }
 
 
@@ -58,9 +62,9 @@ def source_digest(name):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name, bytes_per_launch):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if current."""
-    path = os.path.join(ROOT, "profiles", "traffic_1080p.json")
+def measured_traffic(name, bytes_per_launch, summary="traffic_1080p.json"):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if current."""
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -108,7 +112,7 @@ def ycocg_planes(rgb):
     return torch.stack([y, co, cg], dim=1).reshape(3 * B, Hh, Ww).contiguous()
 
 
-def front_back_stages(rgb, plan, idx, steps, n=4):
+def front_back_stages(rgb, plan, idx, steps, n=4, check_factor1=True):
     """Colour front end and back end on the bench's frames (chroma factor n),
     and the K-frame lowpass filter and its inverse on the step's indices:
     per-kernel time from HIP events, achieved against HBM peak."""
@@ -128,13 +132,17 @@ def front_back_stages(rgb, plan, idx, steps, n=4):
     stats = ct.profile_collect()
     ct.profile_enable(False)
     restored = bool(torch.equal(work, idx))
-    y1, co1, cg1 = ct.rgb_to_ycocg(rgb, 1)
-    exact = bool(torch.equal(ct.ycocg_to_rgb(y1, co1, cg1, 1), rgb.float()))
+    exact = None
+    if check_factor1:
+        y1, co1, cg1 = ct.rgb_to_ycocg(rgb, 1)
+        exact = bool(torch.equal(ct.ycocg_to_rgb(y1, co1, cg1, 1), rgb.float()))
     kern = {}
     for name, (cnt, tms, by) in stats.items():
         gbps = by / (tms / 1e3) / 1e9
         kern[name] = {"avg_launch_us": round(tms / cnt * 1e3, 2), "bytes_per_launch": by / cnt,
-                      "achieved_gbps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4)}
+                      "achieved_gbps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                      "traffic": measured_traffic("lowpass_diff" if name == "lowpass_undiff" else name,
+                                                  by / cnt, "traffic_colour_1080p.json")}
     B, Hh, Ww, _ = rgb.shape
     return {"workload": f"{B} x {Ww}x{Hh} RGB frames, chroma factor {n}; K-frame lowpass filter and its "
                         f"inverse on the step's {idx.shape[0]} planes of indices",
@@ -202,8 +210,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-separate", action="store_true",
                     help="skip timing the four separate calls (profiling runs)")
-    ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
-                    help="copy: stream 1 GiB through a plain elementwise kernel (counter calibration)")
+    ap.add_argument("--mode", choices=["bench", "copy", "colour"], default="bench",
+                    help="copy: stream 1 GiB through a plain elementwise kernel (counter calibration); "
+                         "colour: only the colour and K-frame stages, --steps launches of each")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -222,6 +231,20 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
                           "launches": args.steps}))
+        return
+
+    if args.mode == "colour":
+        # the colour and K-frame stages alone, every launch at chroma factor 4
+        # (for their kernel traces and counters); the lowpass indices come
+        # from the 16 Y planes, each encoded three times
+        rgb = torch.from_numpy(synth.clip_rgb(FRAMES, H, W, 3)).to("cuda:0")
+        plan = ct.Plan(H, W, J, DIRS, PLANES, "cuda:0")
+        steps_tab = synth.subband_steps(plan.nsub, 3, 3)
+        steps = torch.from_numpy(np.stack([steps_tab[b % 3] for b in range(PLANES)])).to("cuda:0")
+        y4, _, _ = ct.rgb_to_ycocg(rgb, 4)
+        idx, _ = plan.encode(y4.repeat(3, 1, 1).contiguous(), steps)
+        fb = front_back_stages(rgb, plan, idx, args.steps, check_factor1=False)
+        print(json.dumps({"mode": "colour", "front_back": fb}))
         return
 
     print(f"[bench] generating {FRAMES} frames of {W}x{H}", file=sys.stderr, flush=True)

@@ -2,6 +2,13 @@
 // pixels (or per lowpass column), blocks mapped XCD-contiguously so that the
 // image rows sharing chroma samples stay in one L2. Built without FMA
 // contraction. The per-thread bodies are in ct_color_stages.h.
+//
+// A thread's group of four pixels is 12 bytes of 8-bit RGB, or 48 bytes of
+// float RGB. A wavefront whose 64 groups are all full moves that interleaved
+// data as contiguous runs instead (lane l takes element l + 64 s of the
+// wave's span), exchanged through a wave-private LDS block, so every global
+// access of the wave covers one contiguous 256-byte (words) or 1 KB
+// (float4) range.
 #include "ct_color.h"
 #include "ct_color_stages.h"
 #include "ct_kernels.h"
@@ -12,13 +19,35 @@ namespace {
 constexpr int NT = 256;
 constexpr int NT_DIFF = 64;   // small lowpass: spread its columns over more CUs
 
+constexpr int kSpan = 3 * 64;   // words (forward) or float4 (inverse) per full wave
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ __launch_bounds__(NT) void rgb_to_ycocg_kernel(const uint8_t* __restrict__ rgb,
                                                           float* __restrict__ y,
                                                           float* __restrict__ co,
                                                           float* __restrict__ cg,
                                                           color::Frame f) {
+    __shared__ uint32_t stage[NT / 64][kSpan];
     const uint32_t t = uint32_t(xcd_remap(blockIdx.x, gridDim.x)) * NT + threadIdx.x;
-    color::rgb_to_ycocg(t, rgb, y, co, cg, f);
+    const uint32_t lane = threadIdx.x & 63, t0 = t - lane;
+    if ((t0 + 64) * color::kPix <= f.P) {   // wave-uniform: all 64 groups full
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(rgb) + 3 * t0;
+        const uint32_t v0 = src[lane], v1 = src[lane + 64], v2 = src[lane + 128];
+        uint32_t* st = stage[threadIdx.x >> 6];
+        st[lane] = v0;
+        st[lane + 64] = v1;
+        st[lane + 128] = v2;
+        wave_sync();
+        const uint32_t w[3] = {st[3 * lane], st[3 * lane + 1], st[3 * lane + 2]};
+        color::rgb_to_ycocg_words(t, w, y, co, cg, f);
+    } else {
+        color::rgb_to_ycocg(t, rgb, y, co, cg, f);
+    }
 }
 
 template <int K>
@@ -27,8 +56,24 @@ __global__ __launch_bounds__(NT) void ycocg_to_rgb_kernel(const float* __restric
                                                           const float* __restrict__ cg,
                                                           float* __restrict__ rgb, color::Frame f,
                                                           float rn) {
+    __shared__ float4 stage[NT / 64][kSpan];
     const uint32_t t = uint32_t(xcd_remap(blockIdx.x, gridDim.x)) * NT + threadIdx.x;
-    color::ycocg_to_rgb<K>(t, y, co, cg, rgb, f, rn);
+    const uint32_t lane = threadIdx.x & 63, t0 = t - lane;
+    float out[3 * color::kPix];
+    const uint32_t cnt = color::rgb_group<K>(t, y, co, cg, f, rn, out);
+    if ((t0 + 64) * color::kPix <= f.P) {   // wave-uniform: all 64 groups full
+        float4* st = stage[threadIdx.x >> 6];
+        st[3 * lane] = make_float4(out[0], out[1], out[2], out[3]);
+        st[3 * lane + 1] = make_float4(out[4], out[5], out[6], out[7]);
+        st[3 * lane + 2] = make_float4(out[8], out[9], out[10], out[11]);
+        wave_sync();
+        float4* dst = reinterpret_cast<float4*>(rgb) + 3 * size_t(t0);
+        dst[lane] = st[lane];
+        dst[lane + 64] = st[lane + 64];
+        dst[lane + 128] = st[lane + 128];
+    } else if (cnt) {
+        color::store_rgb(t, cnt, out, rgb);
+    }
 }
 
 __global__ __launch_bounds__(NT_DIFF) void lowpass_diff_kernel(int16_t* idx, uint32_t plane,

@@ -82,35 +82,13 @@ __host__ __device__ inline float chroma_g(float r, float g, float b) {
     return (-0.25f * r + 0.5f * g - 0.25f * b) + kChromaOffset;
 }
 
-// Forward: thread t converts pixels 4t .. 4t+3 of the batch. `rgb` is
-// 4-byte aligned and `y` 16-byte aligned; a full group reads three words and
-// writes one float4.
-__host__ __device__ inline void rgb_to_ycocg(uint32_t t, const uint8_t* __restrict__ rgb,
-                                             float* __restrict__ y, float* __restrict__ co,
-                                             float* __restrict__ cg, const Frame& f) {
-    const uint32_t p0 = t * kPix;
-    if (p0 >= f.P) return;
-    const uint32_t cnt = f.P - p0 < uint32_t(kPix) ? f.P - p0 : uint32_t(kPix);
-    float r[kPix], g[kPix], b[kPix];
-    if (cnt == kPix) {
-        const uint32_t* w = reinterpret_cast<const uint32_t*>(rgb + 3 * p0);
-        const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
-        const uint32_t bytes[12] = {w0 & 255, (w0 >> 8) & 255, (w0 >> 16) & 255, w0 >> 24,
-                                    w1 & 255, (w1 >> 8) & 255, (w1 >> 16) & 255, w1 >> 24,
-                                    w2 & 255, (w2 >> 8) & 255, (w2 >> 16) & 255, w2 >> 24};
-        for (int k = 0; k < kPix; ++k) {
-            r[k] = float(bytes[3 * k]);
-            g[k] = float(bytes[3 * k + 1]);
-            b[k] = float(bytes[3 * k + 2]);
-        }
-    } else {
-        for (uint32_t k = 0; k < uint32_t(kPix); ++k) {
-            const uint32_t q = k < cnt ? 3 * (p0 + k) : 3 * p0;
-            r[k] = float(rgb[q]);
-            g[k] = float(rgb[q + 1]);
-            b[k] = float(rgb[q + 2]);
-        }
-    }
+// Converts `cnt` pixels starting at p0 (r, g, b already unpacked): Y for
+// each, and Co, Cg where the pixel is a kept chroma sample. A full group
+// stores Y as one float4 (`y` 16-byte aligned).
+__host__ __device__ inline void ycocg_from(uint32_t p0, uint32_t cnt, const float* r,
+                                           const float* g, const float* b,
+                                           float* __restrict__ y, float* __restrict__ co,
+                                           float* __restrict__ cg, const Frame& f) {
     if (cnt == kPix) {
         float4 v;
         v.x = luma(r[0], g[0], b[0]);
@@ -131,6 +109,44 @@ __host__ __device__ inline void rgb_to_ycocg(uint32_t t, const uint8_t* __restri
         }
         pos.next(f);
     }
+}
+
+// Forward for a full group of thread t whose 12 RGB bytes are the words
+// w[0..2] (little endian: R, G, B of pixel 0 in the low bytes of w[0]).
+__host__ __device__ inline void rgb_to_ycocg_words(uint32_t t, const uint32_t* w,
+                                                   float* __restrict__ y, float* __restrict__ co,
+                                                   float* __restrict__ cg, const Frame& f) {
+    float r[kPix], g[kPix], b[kPix];
+    for (int k = 0; k < kPix; ++k) {
+        const int q0 = 3 * k, q1 = 3 * k + 1, q2 = 3 * k + 2;
+        r[k] = float((w[q0 >> 2] >> (8 * (q0 & 3))) & 255);
+        g[k] = float((w[q1 >> 2] >> (8 * (q1 & 3))) & 255);
+        b[k] = float((w[q2 >> 2] >> (8 * (q2 & 3))) & 255);
+    }
+    ycocg_from(t * kPix, kPix, r, g, b, y, co, cg, f);
+}
+
+// Forward: thread t converts pixels 4t .. 4t+3 of the batch. `rgb` is
+// 4-byte aligned; a full group reads three words.
+__host__ __device__ inline void rgb_to_ycocg(uint32_t t, const uint8_t* __restrict__ rgb,
+                                             float* __restrict__ y, float* __restrict__ co,
+                                             float* __restrict__ cg, const Frame& f) {
+    const uint32_t p0 = t * kPix;
+    if (p0 >= f.P) return;
+    const uint32_t cnt = f.P - p0 < uint32_t(kPix) ? f.P - p0 : uint32_t(kPix);
+    if (cnt == kPix) {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(rgb + 3 * p0);
+        const uint32_t w[3] = {src[0], src[1], src[2]};
+        rgb_to_ycocg_words(t, w, y, co, cg, f);
+        return;
+    }
+    float r[kPix], g[kPix], b[kPix];
+    for (uint32_t k = 0; k < cnt; ++k) {
+        r[k] = float(rgb[3 * (p0 + k)]);
+        g[k] = float(rgb[3 * (p0 + k) + 1]);
+        b[k] = float(rgb[3 * (p0 + k) + 2]);
+    }
+    ycocg_from(p0, cnt, r, g, b, y, co, cg, f);
 }
 
 // Float at a byte offset from a uniform base (32-bit offsets let the
@@ -178,8 +194,9 @@ __host__ __device__ inline void to_rgb(float* out, int k, float yv, float o, flo
 // n >= 3, plus the right neighbour of the last.
 __host__ __device__ constexpr int window_cols(int n) { return n == 1 ? 5 : n == 2 ? 4 : 3; }
 
-// Inverse: thread t reconstructs pixels 4t .. 4t+3 as float RGB. `y` and
-// `rgb` are 16-byte aligned; a full group reads one float4 and writes three.
+// Inverse: thread t reconstructs pixels 4t .. 4t+3 as float RGB into
+// out[0..11] and returns how many it covers (0 past the end). `y` is
+// 16-byte aligned; a full group reads one float4.
 // `rn` is 1/n rounded to float32: the interpolation weights are (y mod n)/n
 // and (x mod n)/n. A full group inside one row (the common case) loads a
 // window of K = window_cols(n) chroma columns from the two sample rows, all
@@ -187,12 +204,12 @@ __host__ __device__ constexpr int window_cols(int n) { return n == 1 ? 5 : n == 
 // The per-pixel path for the other groups runs the same float32 operations,
 // so a pixel's value does not depend on the path.
 template <int K>
-__host__ __device__ inline void ycocg_to_rgb(uint32_t t, const float* __restrict__ y,
-                                             const float* __restrict__ co,
-                                             const float* __restrict__ cg, float* __restrict__ rgb,
-                                             const Frame& f, float rn) {
+__host__ __device__ inline uint32_t rgb_group(uint32_t t, const float* __restrict__ y,
+                                              const float* __restrict__ co,
+                                              const float* __restrict__ cg, const Frame& f,
+                                              float rn, float* out /* [3 * kPix] */) {
     const uint32_t p0 = t * kPix;
-    if (p0 >= f.P) return;
+    if (p0 >= f.P) return 0;
     const uint32_t cnt = f.P - p0 < uint32_t(kPix) ? f.P - p0 : uint32_t(kPix);
     float yv[kPix];
     if (cnt == kPix) {
@@ -204,7 +221,6 @@ __host__ __device__ inline void ycocg_to_rgb(uint32_t t, const float* __restrict
     } else {
         for (uint32_t k = 0; k < uint32_t(kPix); ++k) yv[k] = y[k < cnt ? p0 + k : p0];
     }
-    float out[3 * kPix];
     Pos pos;
     pos.init(p0, f);
     if (cnt == kPix && pos.x + (kPix - 1) < uint32_t(f.W)) {
@@ -228,6 +244,10 @@ __host__ __device__ inline void ycocg_to_rgb(uint32_t t, const float* __restrict
         }
         uint32_t xm = pos.xm, jr = 0;
         for (int k = 0; k < kPix; ++k) {
+            if (K == window_cols(1)) {   // n = 1: pixel k sits on sample column k, weight 0
+                xm = 0;
+                jr = uint32_t(k);
+            }
             const float fx = float(xm) * rn;
             to_rgb(out, k, yv[k], hmix(pick(ov, jr), pick(ov, jr + 1), fx),
                    hmix(pick(gv, jr), pick(gv, jr + 1), fx));
@@ -244,14 +264,32 @@ __host__ __device__ inline void ycocg_to_rgb(uint32_t t, const float* __restrict
             if (k + 1 < cnt) pos.next(f);
         }
     }
+    return cnt;
+}
+
+// Stores the `cnt` pixels of thread t's group (three float4 for a full
+// group; `rgb` 16-byte aligned).
+__host__ __device__ inline void store_rgb(uint32_t t, uint32_t cnt, const float* out,
+                                          float* __restrict__ rgb) {
+    const size_t o = 3 * size_t(t) * kPix;
     if (cnt == kPix) {
-        float4* o4 = reinterpret_cast<float4*>(rgb + 3 * size_t(p0));
+        float4* o4 = reinterpret_cast<float4*>(rgb + o);
         o4[0] = make_float4(out[0], out[1], out[2], out[3]);
         o4[1] = make_float4(out[4], out[5], out[6], out[7]);
         o4[2] = make_float4(out[8], out[9], out[10], out[11]);
     } else {
-        for (uint32_t k = 0; k < 3 * cnt; ++k) rgb[3 * size_t(p0) + k] = out[k];
+        for (uint32_t k = 0; k < 3 * cnt; ++k) rgb[o + k] = out[k];
     }
+}
+
+template <int K>
+__host__ __device__ inline void ycocg_to_rgb(uint32_t t, const float* __restrict__ y,
+                                             const float* __restrict__ co,
+                                             const float* __restrict__ cg, float* __restrict__ rgb,
+                                             const Frame& f, float rn) {
+    float out[3 * kPix];
+    const uint32_t cnt = rgb_group<K>(t, y, co, cg, f, rn, out);
+    if (cnt) store_rgb(t, cnt, out, rgb);
 }
 
 // K-frame lowpass filtering in place, thread t owning one column of one
