@@ -150,6 +150,39 @@ def front_back_stages(rgb, plan, idx, steps, n=4, check_factor1=True):
             "lowpass_roundtrip_exact": restored, "colour_roundtrip_exact_factor1": exact}
 
 
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: 32-bit VALU lane-ops/s
+
+
+def motion_stage(planes, steps, w=8):
+    """Full-search block matching (16 x 16 blocks, +-w) of each Y plane of the
+    batch against the one before: per-launch time from HIP events, against the
+    VALU issue rate at one lane-op per candidate pixel (a packed 16-bit
+    subtraction and a 16-bit dot product handle two)."""
+    import torch
+    from paper_1510_00561_amd import ct
+    y = planes[0::3]
+    cur, prev = y[1:].contiguous(), y[:-1].contiguous()
+    mv, ssd = ct.motion_search(cur, prev, w)
+    torch.cuda.synchronize()
+    ct.profile_enable(True, 1024)
+    for _ in range(steps):
+        ct.motion_search(cur, prev, w, mv, ssd)
+    torch.cuda.synchronize()
+    stats = ct.profile_collect()
+    ct.profile_enable(False)
+    cnt, tms, _ = stats["motion_search"]
+    B, Hh, Ww = cur.shape
+    evals = B * (2 * w + 1) ** 2 * Hh * Ww          # candidate pixels per launch
+    us = tms / cnt * 1e3
+    rate = evals / (us * 1e-6)
+    return {"workload": f"{B} pairs of consecutive {Ww}x{Hh} Y planes, 16x16 blocks, w={w} "
+                        f"({(2 * w + 1) ** 2} candidates)",
+            "avg_launch_us": round(us, 2), "pairs_per_s": round(B / (us * 1e-6), 1),
+            "roofline": {"bound": "alu", "achieved": round(rate / 1e12, 3), "peak": VALU_LANE_OPS / 1e12,
+                         "unit": "T candidate-pixels/s", "frac": round(rate / VALU_LANE_OPS, 4)},
+            "moving_blocks": int((mv != 0).any(dim=-1).sum())}
+
+
 def batched_comparison(steps):
     """Mixed workload: 64 streams (one YCoCg frame each) of 320x240, 640x480 or
     1280x720, LP depth 2-4, 8-16 directions, as one graph launch of grouped
@@ -210,9 +243,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-separate", action="store_true",
                     help="skip timing the four separate calls (profiling runs)")
-    ap.add_argument("--mode", choices=["bench", "copy", "colour"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "copy", "colour", "motion"], default="bench",
                     help="copy: stream 1 GiB through a plain elementwise kernel (counter calibration); "
-                         "colour: only the colour and K-frame stages, --steps launches of each")
+                         "colour: only the colour and K-frame stages, --steps launches of each; "
+                         "motion: only the motion search, --steps launches")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -231,6 +265,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
                           "launches": args.steps}))
+        return
+
+    if args.mode == "motion":
+        rgb = torch.from_numpy(synth.clip_rgb(FRAMES, H, W, 3)).to("cuda:0")
+        print(json.dumps({"mode": "motion", "motion": motion_stage(ycocg_planes(rgb), args.steps)}))
         return
 
     if args.mode == "colour":
@@ -338,6 +377,8 @@ def main():
 
     print("[bench] colour and K-frame stages", file=sys.stderr, flush=True)
     fb = front_back_stages(rgb, plan, idx, max(3, args.steps // 2))
+    print("[bench] motion search", file=sys.stderr, flush=True)
+    me = motion_stage(x, max(3, args.steps // 2))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -365,6 +406,7 @@ def main():
         "kernels": kernels,
         "batched": batched,
         "front_back": fb,
+        "motion": me,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -312,6 +312,34 @@ int ct_lowpass_diff(const ct_geom* geom, int32_t batch, int16_t* idx, int32_t in
                     hipStream_t stream);
 
 /*
+ * Full-search block-matching motion estimation on luminance (paper section
+ * 3.2). Conventions as above; no workspace.
+ *   batch, height, width  B frame pairs of H x W pixels (B >= 0, H, W >= 1,
+ *                         B * H * W < 2^31).
+ *   w                     search range, 1..16: displacements (dy, dx) with
+ *                         |dy|, |dx| <= w, (2w + 1)^2 candidates.
+ *   cur, prev             float32 [B][H][W]: plane b of `cur` is matched
+ *                         against plane b of `prev` (for a clip of frames
+ *                         F, pass F[1:] and F[:-1]). Values are taken on
+ *                         the 8-bit scale in steps of 1/4, as
+ *                         ct_rgb_to_ycocg produces them: rounded to the
+ *                         nearest quarter (halves to even), clamped to
+ *                         [0, 255].
+ *   mv                    int16 [B][nby][nbx][2] output, nby = ceil(H/16),
+ *                         nbx = ceil(W/16): (dy, dx) of each 16 x 16 block
+ *                         (edge blocks cropped to the frame). Block (y, x)
+ *                         of cur matches the block at (y + dy, x + dx) of
+ *                         prev, which lies wholly inside the frame.
+ *   ssd                   int32 [B][nby][nbx] output, or NULL: the winning
+ *                         sum of squared differences of 4 Y (16 times that
+ *                         of Y; the MSE is ssd / (16 * block pixels)).
+ * The winner is the smallest sum (equivalently MSE), ties broken by the
+ * smallest |dy| + |dx|, then dy, then dx: the result is exact and unique.
+ */
+int ct_motion_search(int32_t batch, int32_t height, int32_t width, int32_t w, const float* cur,
+                     const float* prev, int16_t* mv, int32_t* ssd, hipStream_t stream);
+
+/*
  * Per-kernel timing (HIP events), for benchmarks and tracing.
  * ct_profile_enable(1) creates a pool of `max_launches` event pairs (0 picks
  * 16384) and makes every later launch record one event before and one after

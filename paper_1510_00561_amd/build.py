@@ -26,6 +26,8 @@ SOURCES = [
     ("ct_batched.hip", ["-ffp-contract=off"]),
     ("ct_color_api.cpp", []),
     ("ct_color.hip", ["-ffp-contract=off"]),
+    ("ct_motion_api.cpp", []),
+    ("ct_motion.hip", []),
 ]
 
 COMMON = [

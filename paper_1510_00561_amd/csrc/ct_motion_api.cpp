@@ -1,0 +1,48 @@
+// C ABI of the block-matching motion search: validation on the host, then
+// one launch (kernel in ct_motion.hip).
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
+
+#include "ct_motion.h"
+#include "ct_plan_internal.h"
+
+namespace {
+
+bool fault_injected() {
+    const char* f = getenv("CT_FAULT_INJECT");
+    return f && strcmp(f, "launch") == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ct_motion_search(int32_t batch, int32_t height, int32_t width, int32_t w, const float* cur,
+                     const float* prev, int16_t* mv, int32_t* ssd, hipStream_t stream) {
+    if (batch < 0 || height < 1 || width < 1 || w < 1 || w > ct::kMotionMaxW) return CT_ERR_ARG;
+    const int64_t pixels = int64_t(batch) * height * width;
+    if (pixels >= (int64_t(1) << 31)) return CT_ERR_ARG;
+    if (batch == 0) return CT_OK;
+    if (!cur || !prev || !mv) return CT_ERR_ARG;
+    if (fault_injected()) return CT_ERR_HIP;
+    ct::MotionArgs a;
+    a.cur = cur;
+    a.prev = prev;
+    a.mv = mv;
+    a.ssd = ssd;
+    a.H = height;
+    a.W = width;
+    a.w = w;
+    a.nby = (height + ct::kMotionBlock - 1) / ct::kMotionBlock;
+    a.nbx = (width + ct::kMotionBlock - 1) / ct::kMotionBlock;
+    a.items = int(int64_t(batch) * a.nby * a.nbx);
+    a.lds_per_wave = int(ct::motion_lds_per_wave(w));
+    // compulsory bytes: both planes read once, the vectors (and sums) written once
+    const double bytes = 8.0 * double(pixels) + a.items * (4.0 + (ssd ? 4.0 : 0.0));
+    CT_PROFILED("motion_search", bytes, ct::launch_motion_search(a, stream), stream);
+    return CT_OK;
+}
+
+}  // extern "C"

@@ -7,7 +7,7 @@ missing or a call fails, an exception is raised.
 
 Names follow the C ABI (include/ct.h): forward, inverse, quantize,
 dequantize, forward_adjoint, inverse_adjoint, layout, rgb_to_ycocg,
-ycocg_to_rgb, lowpass_diff.
+ycocg_to_rgb, lowpass_diff, motion_search.
 """
 import ctypes
 import os
@@ -101,6 +101,7 @@ def _lib():
             "ct_rgb_to_ycocg": [i32, i32, i32, i32, P, P, P, P, P],
             "ct_ycocg_to_rgb": [i32, i32, i32, i32, P, P, P, P, P],
             "ct_lowpass_diff": [G, i32, P, i32, P],
+            "ct_motion_search": [i32, i32, i32, i32, P, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -379,6 +380,30 @@ def ycocg_to_rgb(y, co, cg, n, out=None):
                                 ctypes.c_void_p(out.data_ptr()), st)
     _check("ct_ycocg_to_rgb", rc)
     return out
+
+
+def motion_search(cur, prev, w, mv=None, ssd=None, want_ssd=True):
+    """Block matching of cur [B, H, W] against prev [B, H, W] (float32 luminance):
+    (mv [B, nby, nbx, 2] int16 (dy, dx), ssd [B, nby, nbx] int32 or None)."""
+    if cur.dim() != 3:
+        raise ValueError("cur must be [B, H, W]")
+    B, H, W = cur.shape
+    nby, nbx = -(-H // 16), -(-W // 16)
+    _cuda(cur, torch.float32, (B, H, W), "cur")
+    _cuda(prev, torch.float32, (B, H, W), "prev")
+    mv = torch.empty((B, nby, nbx, 2), dtype=torch.int16, device=cur.device) if mv is None else mv
+    _cuda(mv, torch.int16, (B, nby, nbx, 2), "mv")
+    if want_ssd:
+        ssd = torch.empty((B, nby, nbx), dtype=torch.int32, device=cur.device) if ssd is None else ssd
+        _cuda(ssd, torch.int32, (B, nby, nbx), "ssd")
+    else:
+        ssd = None
+    st = ctypes.c_void_p(torch.cuda.current_stream(cur.device).cuda_stream)
+    rc = _lib().ct_motion_search(B, H, W, int(w), ctypes.c_void_p(cur.data_ptr()),
+                                 ctypes.c_void_p(prev.data_ptr()), ctypes.c_void_p(mv.data_ptr()),
+                                 ctypes.c_void_p(ssd.data_ptr() if ssd is not None else None), st)
+    _check("ct_motion_search", rc)
+    return mv, ssd
 
 
 class Batched:

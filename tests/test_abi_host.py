@@ -116,6 +116,7 @@ def test_fault_injection_hook(ct, monkeypatch):
     assert lib.ct_rgb_to_ycocg(1, 4, 4, 2, dummy, dummy, dummy, dummy, None) == -4
     assert lib.ct_ycocg_to_rgb(1, 4, 4, 2, dummy, dummy, dummy, dummy, None) == -4
     assert lib.ct_lowpass_diff(ctypes.byref(g), 1, dummy, 1, None) == -4
+    assert lib.ct_motion_search(1, 16, 16, 8, dummy, dummy, dummy, None, None) == -4
     assert lib.ct_strerror(-4) == b"HIP runtime error"
 
 
@@ -174,3 +175,17 @@ def test_colour_and_lowpass_validation(ct):
     assert lib.ct_lowpass_diff(ctypes.byref(g), 0, None, 0, None) == 0
     bad = ct.geom(256, 256, 2, [8, 6])
     assert lib.ct_lowpass_diff(ctypes.byref(bad), 1, d4, 0, None) == -2
+
+
+def test_motion_search_validation(ct):
+    lib = ct._lib()
+    d = ctypes.c_void_p(0x1000)
+    f = lib.ct_motion_search
+    assert f(0, 16, 16, 8, None, None, None, None, None) == 0     # empty batch
+    assert f(1, 16, 16, 0, d, d, d, d, None) == -1                # w < 1
+    assert f(1, 16, 16, 17, d, d, d, d, None) == -1               # w > 16
+    assert f(1, 0, 16, 8, d, d, d, d, None) == -1
+    assert f(-1, 16, 16, 8, d, d, d, d, None) == -1
+    assert f(1, 16, 16, 8, None, d, d, d, None) == -1
+    assert f(1, 16, 16, 8, d, d, None, d, None) == -1
+    assert f(1 << 12, 1 << 10, 1 << 10, 8, d, d, d, d, None) == -1   # 2^32 pixels
