@@ -46,6 +46,7 @@ KERNEL_SOURCES = {   # the kernel's code and the host code that sets its launch 
     "ycocg_to_rgb": ("ct_color.hip", "ct_color_stages.h", "ct_color_api.cpp"),
     "lowpass_diff": ("ct_color.hip", "ct_color_stages.h", "ct_color_api.cpp"),
     "lowpass_undiff": ("ct_color.hip", "ct_color_stages.h", "ct_color_api.cpp"),
+    "motion_search": ("ct_motion.hip", "ct_motion.h", "ct_motion_api.cpp"),
 }
 
 

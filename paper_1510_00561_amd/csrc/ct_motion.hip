@@ -50,29 +50,35 @@ __device__ __forceinline__ void wave_sync() {
 
 // Sum of squared differences of one candidate; `cur` holds the block's
 // pairs (row r at 8 r), `ref` the window copy whose pair `k0` starts at the
-// candidate's first column, `rp` the window's row pitch in pairs. With MASK,
-// mask[k] keeps only the block's own columns of pair k.
-template <bool MASK>
+// candidate's first column, `rp` the window's row pitch in pairs. ROWS > 0
+// fixes the row count (full blocks); with MASK, mask[k] keeps only the
+// block's own columns of pair k. Four accumulators keep the dot products of
+// a row independent (integer sums: the order does not matter).
+template <bool MASK, int ROWS>
 __device__ __forceinline__ int candidate_ssd(const uint32_t* cur, const uint32_t* ref, int rr0,
                                              int k0, int rp, int bh, const uint32_t* mask) {
-    int acc = 0;
-    for (int r = 0; r < bh; ++r) {
+    int acc[4] = {0, 0, 0, 0};
+    const int rows = ROWS > 0 ? ROWS : bh;
+#pragma unroll 2
+    for (int r = 0; r < rows; ++r) {
+        const uint32_t* rw = ref + (rr0 + r) * rp + k0;
+        uint32_t rv[kPairs];
+#pragma unroll
+        for (int k = 0; k < kPairs; ++k) rv[k] = rw[k];
         const uint4 c0 = *reinterpret_cast<const uint4*>(cur + kPairs * r);
         const uint4 c1 = *reinterpret_cast<const uint4*>(cur + kPairs * r + 4);
         const uint32_t c[kPairs] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-        const uint32_t* rw = ref + (rr0 + r) * rp + k0;
 #pragma unroll
         for (int k = 0; k < kPairs; ++k) {
-            uint32_t rv = rw[k];
-            uint32_t cv = c[k];
+            uint32_t cv = c[k], v = rv[k];
             if (MASK) {
-                rv &= mask[k];
                 cv &= mask[k];
+                v &= mask[k];
             }
-            acc = ssd_pair(cv, rv, acc);
+            acc[k & 3] = ssd_pair(cv, v, acc[k & 3]);
         }
     }
-    return acc;
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 __global__ __launch_bounds__(NT) void motion_search_kernel(MotionArgs a) {
@@ -119,6 +125,7 @@ __global__ __launch_bounds__(NT) void motion_search_kernel(MotionArgs a) {
     for (int k = 0; k < kPairs; ++k)
         mask[k] = 2 * k + 2 <= bw ? 0xFFFFFFFFu : (2 * k + 1 == bw ? 0x0000FFFFu : 0u);
 
+    const bool full = bh == kB && bw == kB;   // wave-uniform
     const int side = 2 * w + 1, nc = side * side;
     uint64_t best = ~uint64_t(0);
     for (int c0 = 0; c0 < nc; c0 += 64) {
@@ -128,8 +135,8 @@ __global__ __launch_bounds__(NT) void motion_search_kernel(MotionArgs a) {
                            y0 + dy + bh <= a.H && x0 + dx + bw <= a.W;
         const int sc = dx + w;                           // window column of the first pixel
         const uint32_t* ref = (sc & 1) ? odd : even;
-        const int ssd = bw == kB ? candidate_ssd<false>(cur, ref, dy + w, sc >> 1, rp, bh, mask)
-                                 : candidate_ssd<true>(cur, ref, dy + w, sc >> 1, rp, bh, mask);
+        const int ssd = full ? candidate_ssd<false, kB>(cur, ref, dy + w, sc >> 1, rp, bh, mask)
+                             : candidate_ssd<true, 0>(cur, ref, dy + w, sc >> 1, rp, bh, mask);
         const uint64_t key = (uint64_t(uint32_t(ssd)) << 32) |
                              (uint64_t(abs(dy) + abs(dx)) << 16) | (uint64_t(dy + w) << 8) |
                              uint64_t(dx + w);
