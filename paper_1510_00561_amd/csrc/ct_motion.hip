@@ -9,8 +9,9 @@
 // the 8-bit scale: exact for the quarter-integer luminance of the YCoCg
 // front end), each window row twice: as pairs starting at even columns and
 // as pairs starting at odd ones, so that a candidate at any column offset
-// reads aligned pairs. Each lane then takes candidates l, l + 64, ... and
-// accumulates its squared differences two pixels at a time: one packed
+// reads aligned pairs. Each lane then takes tasks l, l + 64, ...: two
+// candidates on one row offset, two columns apart, sharing their window
+// reads, and accumulates their squared differences two pixels at a time: one packed
 // 16-bit subtraction and one 16-bit dot product with 32-bit accumulation per
 // pair (exact: at most 256 * 1020^2 < 2^31). The block's row of 16 pixels
 // is a wave-uniform LDS broadcast. The winner is the smallest 64-bit key
@@ -48,37 +49,54 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sum of squared differences of one candidate; `cur` holds the block's
-// pairs (row r at 8 r), `ref` the window copy whose pair `k0` starts at the
-// candidate's first column, `rp` the window's row pitch in pairs. ROWS > 0
-// fixes the row count (full blocks); with MASK, mask[k] keeps only the
-// block's own columns of pair k. Four accumulators keep the dot products of
-// a row independent (integer sums: the order does not matter).
+// Sums of squared differences of two candidates on one window row offset
+// and two columns apart (same column parity), which share their window
+// reads: `ref` is the window copy of that parity, the first candidate's row
+// `rr0` and pair `k0`; the second reads pairs k0 + 1 .. k0 + 8. `cur` holds
+// the block's pairs (row r at 8 r), `rp` is the window's row pitch in pairs.
+// ROWS > 0 fixes the row count (full blocks); with MASK, mask[k] keeps only
+// the block's own columns of pair k. Two accumulators per candidate keep the
+// dot products of a row independent (integer sums: the order does not
+// matter).
 template <bool MASK, int ROWS>
-__device__ __forceinline__ int candidate_ssd(const uint32_t* cur, const uint32_t* ref, int rr0,
-                                             int k0, int rp, int bh, const uint32_t* mask) {
-    int acc[4] = {0, 0, 0, 0};
+__device__ __forceinline__ void candidate_pair_ssd(const uint32_t* cur, const uint32_t* ref,
+                                                   int rr0, int k0, int rp, int bh,
+                                                   const uint32_t* mask, int& sa, int& sb) {
+    int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
     const int rows = ROWS > 0 ? ROWS : bh;
 #pragma unroll 2
     for (int r = 0; r < rows; ++r) {
         const uint32_t* rw = ref + (rr0 + r) * rp + k0;
-        uint32_t rv[kPairs];
+        uint32_t rv[kPairs + 1];
 #pragma unroll
-        for (int k = 0; k < kPairs; ++k) rv[k] = rw[k];
+        for (int k = 0; k <= kPairs; ++k) rv[k] = rw[k];
         const uint4 c0 = *reinterpret_cast<const uint4*>(cur + kPairs * r);
         const uint4 c1 = *reinterpret_cast<const uint4*>(cur + kPairs * r + 4);
         const uint32_t c[kPairs] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
 #pragma unroll
         for (int k = 0; k < kPairs; ++k) {
-            uint32_t cv = c[k], v = rv[k];
+            uint32_t cv = c[k], va = rv[k], vb = rv[k + 1];
             if (MASK) {
                 cv &= mask[k];
-                v &= mask[k];
+                va &= mask[k];
+                vb &= mask[k];
             }
-            acc[k & 3] = ssd_pair(cv, v, acc[k & 3]);
+            if (k & 1) {
+                a1 = ssd_pair(cv, va, a1);
+                b1 = ssd_pair(cv, vb, b1);
+            } else {
+                a0 = ssd_pair(cv, va, a0);
+                b0 = ssd_pair(cv, vb, b0);
+            }
         }
     }
-    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    sa = a0 + a1;
+    sb = b0 + b1;
+}
+
+__device__ __forceinline__ uint64_t match_key(int ssd, int dy, int dx, int w) {
+    return (uint64_t(uint32_t(ssd)) << 32) | (uint64_t(abs(dy) + abs(dx)) << 16) |
+           (uint64_t(dy + w) << 8) | uint64_t(dx + w);
 }
 
 __global__ __launch_bounds__(NT) void motion_search_kernel(MotionArgs a) {
@@ -98,26 +116,57 @@ __global__ __launch_bounds__(NT) void motion_search_kernel(MotionArgs a) {
     const float* prev = a.prev + int64_t(b) * a.H * a.W;
     const float* curp = a.cur + int64_t(b) * a.H * a.W;
 
-    // search window: row r is previous-plane row y0 - w + r, lane l its column x0 - w + l
-    for (int r = 0; r < S; ++r) {
-        const int gy = y0 - w + r, gx = x0 - w + lane;
-        uint32_t v = 0;
-        if (lane < S && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = quarter(prev[gy * a.W + gx]);
-        uint32_t v1 = __shfl_down(v, 1);
-        if (lane + 1 >= S) v1 = 0;
-        const uint32_t pr = v | (v1 << 16);
-        if (lane < S) {
-            if ((lane & 1) == 0) even[r * rp + (lane >> 1)] = pr;
-            else odd[r * rp + (lane >> 1)] = pr;
+    // Search window: row r is previous-plane row y0 - w + r, column c is
+    // x0 - w + c. A load covers 64 / S rows (lane l: row l / S, column l % S);
+    // eight loads are issued before any is used, from addresses clamped into
+    // the frame (no branch around a load, so all eight stay in flight), and
+    // values outside the frame become 0.
+    const int rpi = 64 / S, lr = lane / S, lc = lane - lr * S;
+    const bool lane_on = lr < rpi;
+    const int iters = (S + rpi - 1) / rpi;
+    for (int i0 = 0; i0 < iters; i0 += 8) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int r = (i0 + j) * rpi + lr;
+            const int gy = min(max(y0 - w + r, 0), a.H - 1), gx = min(max(x0 - w + lc, 0), a.W - 1);
+            v[j] = prev[gy * a.W + gx];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int r = (i0 + j) * rpi + lr, gy = y0 - w + r, gx = x0 - w + lc;
+            const bool on = lane_on && r < S;
+            const uint32_t q = on && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W ? quarter(v[j]) : 0u;
+            uint32_t q1 = __shfl_down(q, 1);
+            if (lc + 1 >= S) q1 = 0;
+            if (on) {
+                if ((lc & 1) == 0) even[r * rp + (lc >> 1)] = q | (q1 << 16);
+                else odd[r * rp + (lc >> 1)] = q | (q1 << 16);
+            }
         }
     }
-    // the block: four rows per pass, lane l at row 4 i + l / 16, column l % 16
-    for (int i = 0; i < kB / 4; ++i) {
-        const int r = 4 * i + (lane >> 4), cx = lane & 15;
-        uint32_t v = 0;
-        if (r < bh && cx < bw) v = quarter(curp[(y0 + r) * a.W + x0 + cx]);
-        const uint32_t v1 = __shfl_down(v, 1);
-        if ((cx & 1) == 0) cur[kPairs * r + (cx >> 1)] = v | (v1 << 16);
+    // the pad pair past each window row (read, then discarded, by the second
+    // candidate of a task whose first one is the last column)
+    if (lane < S) {
+        even[lane * rp + S / 2] = 0;
+        odd[lane * rp + S / 2] = 0;
+    }
+    // the block: four rows per load, lane l at row 4 i + l / 16, column l % 16
+    {
+        const int cx = lane & 15;
+        float v[kB / 4];
+#pragma unroll
+        for (int i = 0; i < kB / 4; ++i) {
+            const int r = min(4 * i + (lane >> 4), bh - 1);
+            v[i] = curp[(y0 + r) * a.W + x0 + min(cx, bw - 1)];
+        }
+#pragma unroll
+        for (int i = 0; i < kB / 4; ++i) {
+            const int r = 4 * i + (lane >> 4);
+            const uint32_t q = r < bh && cx < bw ? quarter(v[i]) : 0u;
+            const uint32_t q1 = __shfl_down(q, 1);
+            if ((cx & 1) == 0) cur[kPairs * r + (cx >> 1)] = q | (q1 << 16);
+        }
     }
     wave_sync();
 
@@ -125,22 +174,26 @@ __global__ __launch_bounds__(NT) void motion_search_kernel(MotionArgs a) {
     for (int k = 0; k < kPairs; ++k)
         mask[k] = 2 * k + 2 <= bw ? 0xFFFFFFFFu : (2 * k + 1 == bw ? 0x0000FFFFu : 0u);
 
+    // Tasks: one window row offset (dy) and a column offset sc = dx + w with
+    // sc mod 4 in {0, 1}, paired with sc + 2; tpr tasks per row cover every
+    // sc in [0, 2w] once.
     const bool full = bh == kB && bw == kB;   // wave-uniform
-    const int side = 2 * w + 1, nc = side * side;
+    const int side = 2 * w + 1, tpr = 2 * (side / 4) + min(side % 4, 2), nt = side * tpr;
     uint64_t best = ~uint64_t(0);
-    for (int c0 = 0; c0 < nc; c0 += 64) {
-        const int c = min(c0 + lane, nc - 1);
-        const int dy = c / side - w, dx = c - (c / side) * side - w;
-        const bool valid = c0 + lane < nc && y0 + dy >= 0 && x0 + dx >= 0 &&
-                           y0 + dy + bh <= a.H && x0 + dx + bw <= a.W;
-        const int sc = dx + w;                           // window column of the first pixel
-        const uint32_t* ref = (sc & 1) ? odd : even;
-        const int ssd = full ? candidate_ssd<false, kB>(cur, ref, dy + w, sc >> 1, rp, bh, mask)
-                             : candidate_ssd<true, 0>(cur, ref, dy + w, sc >> 1, rp, bh, mask);
-        const uint64_t key = (uint64_t(uint32_t(ssd)) << 32) |
-                             (uint64_t(abs(dy) + abs(dx)) << 16) | (uint64_t(dy + w) << 8) |
-                             uint64_t(dx + w);
-        if (valid && key < best) best = key;
+    for (int t0 = 0; t0 < nt; t0 += 64) {
+        const int t = min(t0 + lane, nt - 1), row = t / tpr, u = t - row * tpr;
+        const int dy = row - w, sa = 4 * (u >> 1) + (u & 1), sb = sa + 2;
+        const bool live = t0 + lane < nt && y0 + dy >= 0 && y0 + dy + bh <= a.H;
+        const uint32_t* ref = (sa & 1) ? odd : even;
+        int ssd_a, ssd_b;
+        if (full) candidate_pair_ssd<false, kB>(cur, ref, row, sa >> 1, rp, bh, mask, ssd_a, ssd_b);
+        else candidate_pair_ssd<true, 0>(cur, ref, row, sa >> 1, rp, bh, mask, ssd_a, ssd_b);
+        const int dxa = sa - w, dxb = sb - w;
+        const bool va = live && x0 + dxa >= 0 && x0 + dxa + bw <= a.W;
+        const bool vb = live && sb <= 2 * w && x0 + dxb >= 0 && x0 + dxb + bw <= a.W;
+        const uint64_t ka = match_key(ssd_a, dy, dxa, w), kb = match_key(ssd_b, dy, dxb, w);
+        if (va && ka < best) best = ka;
+        if (vb && kb < best) best = kb;
     }
     for (int off = 32; off >= 1; off >>= 1) {
         const uint64_t o = __shfl_xor(best, off);
