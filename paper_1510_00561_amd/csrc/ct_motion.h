@@ -16,10 +16,14 @@ struct MotionArgs {
     int16_t* mv;          // [B][nby][nbx][2] (dy, dx)
     int32_t* ssd;         // [B][nby][nbx] or null
     int H, W, w, nby, nbx, items;
-    int lds_per_wave;     // 32-bit words of LDS per wavefront
+    // LDS layout per wavefront, in 32-bit words: the even-column pairs of
+    // the window at 0 with row pitch `rp`, the odd-column pairs at `odd_off`
+    // (same pitch), the block's pairs at `cur_off`, `lds_per_wave` in all
+    int rp, odd_off, cur_off, lds_per_wave;
 };
 
-size_t motion_lds_per_wave(int w);
+// Fills the LDS layout of `a` for its search range a.w.
+void motion_layout(MotionArgs* a);
 hipError_t launch_motion_search(const MotionArgs& a, hipStream_t st);
 
 }  // namespace ct

@@ -109,10 +109,10 @@ __global__ __launch_bounds__(NT) void motion_search_kernel(MotionArgs a) {
     const int by = rem / a.nbx, bx = rem - by * a.nbx;
     const int y0 = by * kB, x0 = bx * kB;
     const int bh = min(kB, a.H - y0), bw = min(kB, a.W - x0);
-    const int w = a.w, S = kB + 2 * w, rp = S / 2 + 1;
+    const int w = a.w, S = kB + 2 * w, rp = a.rp;
     uint32_t* even = smem + wave * a.lds_per_wave;      // pair k = columns 2k, 2k + 1
-    uint32_t* odd = even + S * rp;                       // pair k = columns 2k + 1, 2k + 2
-    uint32_t* cur = odd + S * rp;                        // block pairs, 8 per row
+    uint32_t* odd = even + a.odd_off;                    // pair k = columns 2k + 1, 2k + 2
+    uint32_t* cur = even + a.cur_off;                    // block pairs, 8 per row
     const float* prev = a.prev + int64_t(b) * a.H * a.W;
     const float* curp = a.cur + int64_t(b) * a.H * a.W;
 
@@ -209,9 +209,18 @@ __global__ __launch_bounds__(NT) void motion_search_kernel(MotionArgs a) {
 
 }  // namespace
 
-size_t motion_lds_per_wave(int w) {
-    const int S = kB + 2 * w, rp = S / 2 + 1;
-    return size_t(2 * S * rp + kPairs * kB);
+// The window rows hold S / 2 + 1 pairs (the last one a zero pad). At w = 8
+// (the paper's setting) the rows are padded to 21 pairs and the odd copy
+// starts one word later, which halves the bank conflicts of the candidates'
+// window reads (the lanes of a wavefront read pairs two apart on up to eight
+// window rows); other ranges keep the dense layout.
+void motion_layout(MotionArgs* a) {
+    const int S = kB + 2 * a->w;
+    const bool tuned = a->w == 8;
+    a->rp = S / 2 + 1 + (tuned ? 4 : 0);
+    a->odd_off = S * a->rp + (tuned ? 1 : 0);
+    a->cur_off = (a->odd_off + S * a->rp + 3) & ~3;   // 16-byte aligned block rows
+    a->lds_per_wave = a->cur_off + kPairs * kB;
 }
 
 hipError_t launch_motion_search(const MotionArgs& a, hipStream_t st) {

@@ -38,7 +38,7 @@ int ct_motion_search(int32_t batch, int32_t height, int32_t width, int32_t w, co
     a.nby = (height + ct::kMotionBlock - 1) / ct::kMotionBlock;
     a.nbx = (width + ct::kMotionBlock - 1) / ct::kMotionBlock;
     a.items = int(int64_t(batch) * a.nby * a.nbx);
-    a.lds_per_wave = int(ct::motion_lds_per_wave(w));
+    ct::motion_layout(&a);
     // compulsory bytes: both planes read once, the vectors (and sums) written once
     const double bytes = 8.0 * double(pixels) + a.items * (4.0 + (ssd ? 4.0 : 0.0));
     CT_PROFILED("motion_search", bytes, ct::launch_motion_search(a, stream), stream);
