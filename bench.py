@@ -171,7 +171,7 @@ def motion_stage(planes, steps, w=8):
     torch.cuda.synchronize()
     stats = ct.profile_collect()
     ct.profile_enable(False)
-    cnt, tms, _ = stats["motion_search"]
+    cnt, tms, by = stats["motion_search"]
     B, Hh, Ww = cur.shape
     evals = B * (2 * w + 1) ** 2 * Hh * Ww          # candidate pixels per launch
     us = tms / cnt * 1e3
@@ -180,7 +180,9 @@ def motion_stage(planes, steps, w=8):
                         f"({(2 * w + 1) ** 2} candidates)",
             "avg_launch_us": round(us, 2), "pairs_per_s": round(B / (us * 1e-6), 1),
             "roofline": {"bound": "alu", "achieved": round(rate / 1e12, 3), "peak": VALU_LANE_OPS / 1e12,
-                         "unit": "T candidate-pixels/s", "frac": round(rate / VALU_LANE_OPS, 4)},
+                         "unit": "T candidate-pixels/s", "frac": round(rate / VALU_LANE_OPS, 4),
+                         "traffic": measured_traffic("motion_search", by / cnt, "traffic_motion_1080p.json"),
+                         "compulsory_bytes": by / cnt},
             "moving_blocks": int((mv != 0).any(dim=-1).sum())}
 
 
