@@ -20,6 +20,7 @@ constexpr int NT = 256;
 constexpr int NT_DIFF = 64;   // small lowpass: spread its columns over more CUs
 
 constexpr int kSpan = 3 * 64;   // words (forward) or float4 (inverse) per full wave
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -67,10 +68,12 @@ __global__ __launch_bounds__(NT) void ycocg_to_rgb_kernel(const float* __restric
         st[3 * lane + 1] = make_float4(out[4], out[5], out[6], out[7]);
         st[3 * lane + 2] = make_float4(out[8], out[9], out[10], out[11]);
         wave_sync();
-        float4* dst = reinterpret_cast<float4*>(rgb) + 3 * size_t(t0);
-        dst[lane] = st[lane];
-        dst[lane + 64] = st[lane + 64];
-        dst[lane + 128] = st[lane + 128];
+        // the output is written once and not read back here: streaming stores
+        const v4f* sv = reinterpret_cast<const v4f*>(st);
+        v4f* dst = reinterpret_cast<v4f*>(rgb) + 3 * size_t(t0);
+        __builtin_nontemporal_store(sv[lane], dst + lane);
+        __builtin_nontemporal_store(sv[lane + 64], dst + lane + 64);
+        __builtin_nontemporal_store(sv[lane + 128], dst + lane + 128);
     } else if (cnt) {
         color::store_rgb(t, cnt, out, rgb);
     }
