@@ -179,21 +179,44 @@ __global__ __launch_bounds__(NT) void motion_search_kernel(MotionArgs a) {
     // sc in [0, 2w] once.
     const bool full = bh == kB && bw == kB;   // wave-uniform
     const int side = 2 * w + 1, tpr = 2 * (side / 4) + min(side % 4, 2), nt = side * tpr;
+    // A full block whose last pass would hold at most 32 tasks runs that pass
+    // as 2 x tail half-tasks instead: lanes 2i and 2i + 1 take rows 0-7 and
+    // 8-15 of task i and add their sums across the lane pair.
+    const int nfull = nt / 64, tail = nt - 64 * nfull;
+    const bool split = full && tail > 0 && tail <= 32;
+    const int npass = split ? nfull : (nt + 63) / 64;
     uint64_t best = ~uint64_t(0);
-    for (int t0 = 0; t0 < nt; t0 += 64) {
+    auto consider = [&](bool live, int dy, int sa, int ssd_a, int ssd_b) {
+        const int dxa = sa - w, dxb = sa + 2 - w;
+        const bool va = live && x0 + dxa >= 0 && x0 + dxa + bw <= a.W;
+        const bool vb = live && sa + 2 <= 2 * w && x0 + dxb >= 0 && x0 + dxb + bw <= a.W;
+        const uint64_t ka = match_key(ssd_a, dy, dxa, w), kb = match_key(ssd_b, dy, dxb, w);
+        if (va && ka < best) best = ka;
+        if (vb && kb < best) best = kb;
+    };
+    for (int p = 0; p < npass; ++p) {
+        const int t0 = 64 * p;
         const int t = min(t0 + lane, nt - 1), row = t / tpr, u = t - row * tpr;
-        const int dy = row - w, sa = 4 * (u >> 1) + (u & 1), sb = sa + 2;
+        const int dy = row - w, sa = 4 * (u >> 1) + (u & 1);
         const bool live = t0 + lane < nt && y0 + dy >= 0 && y0 + dy + bh <= a.H;
         const uint32_t* ref = (sa & 1) ? odd : even;
         int ssd_a, ssd_b;
         if (full) candidate_pair_ssd<false, kB>(cur, ref, row, sa >> 1, rp, bh, mask, ssd_a, ssd_b);
         else candidate_pair_ssd<true, 0>(cur, ref, row, sa >> 1, rp, bh, mask, ssd_a, ssd_b);
-        const int dxa = sa - w, dxb = sb - w;
-        const bool va = live && x0 + dxa >= 0 && x0 + dxa + bw <= a.W;
-        const bool vb = live && sb <= 2 * w && x0 + dxb >= 0 && x0 + dxb + bw <= a.W;
-        const uint64_t ka = match_key(ssd_a, dy, dxa, w), kb = match_key(ssd_b, dy, dxb, w);
-        if (va && ka < best) best = ka;
-        if (vb && kb < best) best = kb;
+        consider(live, dy, sa, ssd_a, ssd_b);
+    }
+    if (split) {
+        const int i = min(lane >> 1, tail - 1), h = lane & 1;
+        const int t = 64 * nfull + i, row = t / tpr, u = t - row * tpr;
+        const int dy = row - w, sa = 4 * (u >> 1) + (u & 1);
+        const bool live = (lane >> 1) < tail && y0 + dy >= 0 && y0 + dy + bh <= a.H;
+        const uint32_t* ref = (sa & 1) ? odd : even;
+        int ssd_a, ssd_b;
+        candidate_pair_ssd<false, kB / 2>(cur + kPairs * (kB / 2) * h, ref, row + (kB / 2) * h,
+                                          sa >> 1, rp, bh, mask, ssd_a, ssd_b);
+        ssd_a += __shfl_xor(ssd_a, 1);
+        ssd_b += __shfl_xor(ssd_b, 1);
+        consider(live, dy, sa, ssd_a, ssd_b);
     }
     for (int off = 32; off >= 1; off >>= 1) {
         const uint64_t o = __shfl_xor(best, off);
