@@ -1,4 +1,7 @@
 """Pins of the whole contourlet transform (section 2.1 structure, section 3.3 layout)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -9,7 +12,7 @@ from oracle import geometry as geo
 @pytest.mark.parametrize("H,W,J,dirs", [
     (16, 16, 2, [8, 4]),
     (64, 64, 2, [8, 4]),
-    (40, 56, 2, [4, 4]),          # padded
+    (40, 56, 2, [4, 4]),          # unpadded (multiples of 4)
     (72, 96, 3, [16, 8, 4]),      # padded to 72 x 96 (multiples of 8)
     (70, 90, 3, [16, 8, 4]),      # padded to 72 x 96
     (64, 64, 1, [64]),
@@ -118,3 +121,71 @@ def test_adjoints_equal_explicit_transpose_32():
         np.testing.assert_allclose(ct.forward_adjoint(g, H, W, J, dirs).ravel(), M.T @ g, atol=1e-11)
         y = rng.standard_normal(H * W)
         np.testing.assert_allclose(ct.inverse_adjoint(y.reshape(H, W), H, W, J, dirs), S.T @ y, atol=1e-11)
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_padding_worked_example():
+    """The mirror extension on a hand-worked 3 x 4 -> 5 x 7 example."""
+    with open(os.path.join(GOLDEN, "pad_worked.json")) as f:
+        g = json.load(f)
+    x = np.array(g["frame"], dtype=np.float64)
+    R, C = g["padded_rc"]
+    np.testing.assert_array_equal(ct._pad(x, R, C), np.array(g["padded"], dtype=np.float64))
+    np.testing.assert_array_equal(matrix.pad_matrix(*x.shape, R, C) @ x.ravel(),
+                                  np.array(g["padded"], dtype=np.float64).ravel())
+
+
+def test_pad_adjoint_is_transpose():
+    H, W, R, C = 13, 11, 16, 16
+    P = matrix.pad_matrix(H, W, R, C)
+    y = np.random.default_rng(26).standard_normal((R, C))
+    np.testing.assert_allclose(ct._pad_adjoint(y, H, W).ravel(), P.T @ y.ravel(), atol=1e-13)
+
+
+@pytest.fixture(scope="module")
+def padded_matrices():
+    """14 x 18, J = 2, dirs 8/4: padded to 16 x 20 (rows and columns)."""
+    H, W, J, dirs = 14, 18, 2, [8, 4]
+    R, C = geo.padded_size(H, W, J, dirs)
+    assert (R, C) == (16, 20)
+    return (H, W, J, dirs), matrix.forward_matrix(H, W, R, C, J, dirs), matrix.inverse_matrix(H, W, R, C, J, dirs)
+
+
+def test_explicit_matrix_padded(padded_matrices):
+    """The array path equals the stage-by-stage matrices on a padded geometry,
+    so the padding rule (and the crop) are fixed by an independent route."""
+    (H, W, J, dirs), M, S = padded_matrices
+    n = H * W
+    fast = np.stack([ct.forward(np.eye(n)[i].reshape(H, W), J, dirs) for i in range(n)], 1)
+    np.testing.assert_allclose(fast, M, atol=1e-12)
+    nc = M.shape[0]
+    rng = np.random.default_rng(27)
+    for _ in range(3):
+        v = rng.standard_normal(nc)
+        np.testing.assert_allclose(ct.inverse(v, H, W, J, dirs).ravel(), S @ v, atol=1e-11)
+    np.testing.assert_allclose(S @ M, np.eye(n), atol=1e-11)
+
+
+def test_adjoints_explicit_transpose_padded(padded_matrices):
+    (H, W, J, dirs), M, S = padded_matrices
+    rng = np.random.default_rng(28)
+    for _ in range(3):
+        g = rng.standard_normal(M.shape[0])
+        np.testing.assert_allclose(ct.forward_adjoint(g, H, W, J, dirs).ravel(), M.T @ g, atol=1e-11)
+        y = rng.standard_normal(H * W)
+        np.testing.assert_allclose(ct.inverse_adjoint(y.reshape(H, W), H, W, J, dirs), S.T @ y, atol=1e-11)
+
+
+def test_adjoint_dot_products_padded():
+    H, W, J, dirs = 70, 90, 3, [16, 8, 4]
+    rng = np.random.default_rng(29)
+    x = rng.standard_normal((H, W))
+    y = rng.standard_normal(geo.ncoef(H, W, J, dirs))
+    lhs = np.dot(ct.forward(x, J, dirs), y)
+    rhs = np.dot(x.ravel(), ct.forward_adjoint(y, H, W, J, dirs).ravel())
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+    lhs = np.dot(ct.inverse(y, H, W, J, dirs).ravel(), x.ravel())
+    rhs = np.dot(y, ct.inverse_adjoint(x, H, W, J, dirs))
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs)
