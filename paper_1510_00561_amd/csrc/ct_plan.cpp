@@ -9,8 +9,8 @@
 //
 // Autotuning (CT_PLAN_AUTOTUNE) picks, for every distinct LP level shape
 // with four or more DFB tree levels, whether the deeper tree levels run in
-// pairs (64 x 64 sheared tiles) or one at a time (32 x 64 tiles), by timing
-// both with HIP events. Choices are cached in a JSON file keyed by device
+// pairs (one streaming pass per two levels, halo 12) or one at a time (one
+// pass per level, halo 4), by timing both with HIP events. Choices are cached in a JSON file keyed by device
 // architecture and shape (CT_AUTOTUNE_CACHE, default
 // $HOME/.cache/ct_autotune.json).
 #include <stdio.h>

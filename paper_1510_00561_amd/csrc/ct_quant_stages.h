@@ -1,5 +1,5 @@
-// Quantiser stages (device functions), shared by the quantiser kernels and
-// the batched work-queue kernel. The float32 operation order is part of the
+// Quantiser stages (device functions), shared by the quantiser kernels, the
+// group kernels of the batched form and the quantising transform stages. The float32 operation order is part of the
 // contract (ct.h, ct_quantize): every function body disables FMA contraction
 // (the _rn helpers are plain operators in this toolchain configuration).
 //

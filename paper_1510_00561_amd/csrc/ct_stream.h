@@ -1,7 +1,7 @@
 // Register-streaming form of the deeper DFB tree levels (t >= 3), one tree
 // level or two consecutive ones per pass.
 //
-// Every wavefront owns one strip of 256 sheared columns (four adjacent
+// Every wavefront owns one strip of 128 sheared columns (two adjacent
 // columns per lane) of one parent channel and streams down a block of its
 // rows. Rows live in a ring of registers; a lifting step on a row reads its
 // vertical neighbours from the ring and its horizontal neighbours from the

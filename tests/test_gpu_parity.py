@@ -82,8 +82,9 @@ def test_forward_inverse_parity(name, H, W, J, dirs, B):
         ref = oct.forward(x[b].astype(np.float64), J, dirs)
         err = np.abs(coef_h[b] - ref).max()
         assert err <= TOL, f"plane {b}: forward max abs err {err}"
-        # inverse of the oracle's coefficients (as FP32) against the oracle inverse
+        # the GPU round trip restores the input
         assert np.abs(rec_h[b] - x[b]).max() <= TOL
+    # inverse of the oracle's coefficients (as FP32) against the oracle inverse
     ref_c32 = np.stack([oct.forward(x[b].astype(np.float64), J, dirs) for b in range(B)]).astype(np.float32)
     rec2 = plan.inverse(_dev(ref_c32)).cpu().numpy()
     for b in range(B):

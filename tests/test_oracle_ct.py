@@ -13,7 +13,7 @@ from oracle import geometry as geo
     (16, 16, 2, [8, 4]),
     (64, 64, 2, [8, 4]),
     (40, 56, 2, [4, 4]),          # unpadded (multiples of 4)
-    (72, 96, 3, [16, 8, 4]),      # padded to 72 x 96 (multiples of 8)
+    (72, 96, 3, [16, 8, 4]),      # unpadded (multiples of 8)
     (70, 90, 3, [16, 8, 4]),      # padded to 72 x 96
     (64, 64, 1, [64]),
     (33, 65, 1, [4]),
