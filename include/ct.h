@@ -160,6 +160,21 @@ int ct_quantize(const ct_geom* geom, int32_t batch, const float* coeffs, const f
                 void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * ct_quantize without a workspace, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, arithmetic and results as ct_quantize,
+ * minus ws/ws_bytes. Its scratch (the lowpass min/max partials, 2 KiB per
+ * plane) is a static device array that each GPU holds until the process
+ * ends, sized for at most 1024 planes: a larger batch returns
+ * CT_ERR_WORKSPACE with nothing enqueued. The call allocates nothing. Every
+ * call on one GPU shares that GPU's array: calls that overlap in time on one
+ * GPU (unordered streams) race and must be ordered by the caller.
+ */
+int ct_quantize_noalloc(const ct_geom* geom, int32_t batch, const float* coeffs,
+                        const float* steps, int32_t steps_stride, int16_t* idx, float* side,
+                        hipStream_t stream);
+
+/*
  * Dequantise (the decoder side of sections 3.4-3.5):
  *   directional  c = q * step[i]
  *   lowpass      c = mn + (q * step[0]) * ((mx - mn) / 255)

@@ -28,6 +28,7 @@ SOURCES = [
     ("ct_color.hip", ["-ffp-contract=off"]),
     ("ct_motion_api.cpp", []),
     ("ct_motion.hip", []),
+    ("ct_noalloc.hip", []),
 ]
 
 COMMON = [

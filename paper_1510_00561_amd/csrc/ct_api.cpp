@@ -689,6 +689,48 @@ int ct_quantize(const ct_geom* geom, int32_t batch, const float* coeffs, const f
     return launch_chain(chain, stream);
 }
 
+}  // extern "C"
+
+namespace ct {
+
+// Argument checks of ct_quantize (host only).
+int check_quantize(const ct_geom* geom, int32_t batch, const float* coeffs, const float* steps,
+                   int32_t steps_stride, const int16_t* idx, const float* side) {
+    Geometry g;
+    const int rc = check_common(geom, batch, &g);
+    if (rc != CT_OK) return rc;
+    if (batch == 0) return CT_OK;
+    if (!coeffs || !steps || !idx || !side) return CT_ERR_ARG;
+    if (steps_stride < 0 || (steps_stride > 0 && steps_stride < g.nsub)) return CT_ERR_ARG;
+    return CT_OK;
+}
+
+// ct_quantize with the lowpass partials at `partials` (device memory of
+// `partial_bytes` bytes) instead of in a caller workspace.
+int quantize_with_partials(const ct_geom* geom, int32_t batch, const float* coeffs,
+                           const float* steps, int32_t steps_stride, int16_t* idx, float* side,
+                           void* partials, size_t partial_bytes, hipStream_t stream) {
+    int rc = check_quantize(geom, batch, coeffs, steps, steps_stride, idx, side);
+    if (rc != CT_OK || batch == 0) return rc;
+    Geometry g;
+    rc = check_common(geom, batch, &g);
+    if (rc != CT_OK) return rc;
+    if (!partials) return CT_ERR_ARG;
+    if (partial_bytes < quantize_partial_bytes(batch)) return CT_ERR_WORKSPACE;
+    if (fault_injected()) return CT_ERR_HIP;
+    Workspace w;                   // only the partials are used, at offset 0
+    w.part_off = 0;
+    std::vector<StageDesc> chain;
+    rc = build_quant_chain(g, batch, coeffs, steps, steps_stride, idx, side,
+                           static_cast<char*>(partials), w, chain);
+    if (rc != CT_OK) return rc;
+    return launch_chain(chain, stream);
+}
+
+}  // namespace ct
+
+extern "C" {
+
 int ct_dequantize(const ct_geom* geom, int32_t batch, const int16_t* idx, const float* steps,
                   int32_t steps_stride, const float* side, float* coeffs, hipStream_t stream) {
     Geometry g;

@@ -49,6 +49,17 @@ struct Workspace {
 };
 constexpr int kMaxPart = 256;
 Workspace workspace_layout(const Geometry& g, int batch);
+// Bytes of the quantiser's lowpass partials for `batch` planes.
+inline size_t quantize_partial_bytes(int batch) { return size_t(batch) * kMaxPart * 2 * sizeof(float); }
+// Argument validation of ct_quantize (host only, nothing enqueued).
+int check_quantize(const ct_geom* geom, int32_t batch, const float* coeffs, const float* steps,
+                   int32_t steps_stride, const int16_t* idx, const float* side);
+// ct_quantize with its lowpass partials in caller-given device memory of
+// `partial_bytes` bytes (at least quantize_partial_bytes(batch)) in place of
+// the workspace; validation and errors as for ct_quantize.
+int quantize_with_partials(const ct_geom* geom, int32_t batch, const float* coeffs,
+                           const float* steps, int32_t steps_stride, int16_t* idx, float* side,
+                           void* partials, size_t partial_bytes, hipStream_t stream);
 
 // Filters and lifting constants, derived at first use from the closed-form
 // 9-7 pair.

@@ -95,6 +95,7 @@ def _lib():
             "ct_forward_adjoint": [G, i32, P, P, P, sz, P],
             "ct_inverse_adjoint": [G, i32, P, P, P, sz, P],
             "ct_quantize": [G, i32, P, P, i32, P, P, P, sz, P],
+            "ct_quantize_noalloc": [G, i32, P, P, i32, P, P, P],
             "ct_dequantize": [G, i32, P, P, i32, P, P, P],
             "ct_encode": [G, i32, P, P, i32, P, P, P, P, sz, P],
             "ct_decode": [G, i32, P, P, i32, P, P, P, sz, P],
@@ -247,6 +248,25 @@ class Plan:
                                 ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(side.data_ptr()),
                                 ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, self._stream())
         _check("ct_quantize", rc)
+        return idx, side
+
+    def quantize_noalloc(self, coeffs, steps, idx=None, side=None):
+        """ct_quantize_noalloc: as quantize(), with the library's static scratch
+        instead of the plan's workspace (at most 1024 planes)."""
+        B = self.batch
+        self._check_tensor(coeffs, (B, self.ncoef), torch.float32, "coeffs")
+        steps, stride = self._steps(steps)
+        if idx is None:
+            idx = torch.empty((B, self.ncoef), dtype=torch.int16, device=coeffs.device)
+        if side is None:
+            side = torch.empty((B, 2), dtype=torch.float32, device=coeffs.device)
+        self._check_tensor(idx, (B, self.ncoef), torch.int16, "idx")
+        self._check_tensor(side, (B, 2), torch.float32, "side")
+        rc = _lib().ct_quantize_noalloc(ctypes.byref(self.g), B, ctypes.c_void_p(coeffs.data_ptr()),
+                                        ctypes.c_void_p(steps.data_ptr()), stride,
+                                        ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(side.data_ptr()),
+                                        self._stream())
+        _check("ct_quantize_noalloc", rc)
         return idx, side
 
     def dequantize(self, idx, steps, side, out=None):

@@ -189,3 +189,19 @@ def test_motion_search_validation(ct):
     assert f(1, 16, 16, 8, None, d, d, d, None) == -1
     assert f(1, 16, 16, 8, d, d, None, d, None) == -1
     assert f(1 << 12, 1 << 10, 1 << 10, 8, d, d, d, d, None) == -1   # 2^32 pixels
+
+
+def test_quantize_noalloc_validation(ct):
+    # every check runs before the first HIP call, so this runs without a GPU
+    lib = ct._lib()
+    g = ct.geom(256, 256, 2, [8, 4])
+    d = ctypes.c_void_p(0x1000)
+    f = lib.ct_quantize_noalloc
+    assert f(ctypes.byref(g), 0, None, None, 0, None, None, None) == 0    # empty batch
+    assert f(None, 1, d, d, 0, d, d, None) == -1
+    assert f(ctypes.byref(g), -1, d, d, 0, d, d, None) == -1
+    assert f(ctypes.byref(g), 1, None, d, 0, d, d, None) == -1
+    assert f(ctypes.byref(g), 1, d, d, 3, d, d, None) == -1              # stride < nsub
+    assert f(ctypes.byref(g), 1025, d, d, 0, d, d, None) == -3           # beyond the static scratch
+    bad = ct.geom(256, 256, 2, [8, 6])
+    assert f(ctypes.byref(bad), 1, d, d, 0, d, d, None) == -2
