@@ -63,8 +63,36 @@ def test_dot_products_full_size():
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
 
 
+# Worker state of the finite-difference pool: the residual S c - x of every
+# plane, set once per worker process.
+_FD_RESID = None
+
+
+def _fd_init(resid):
+    global _FD_RESID
+    _FD_RESID = resid
+
+
+def _fd_quadratic(args):
+    """Central difference of ||S c - x||^2 along coordinate i of plane b.
+
+    S is linear, so S(c +- h e_i) - x = r +- h S e_i with r = S c - x: the
+    loss at both points needs one oracle inverse, of the unit vector."""
+    b, i, h, ncoef = args
+    e = np.zeros(ncoef)
+    e[i] = 1.0
+    s = oct.inverse(e, H5, W5, J5, D5)
+    r = _FD_RESID[b]
+    plus = r + h * s
+    minus = r - h * s
+    return (float(np.sum(plus * plus)) - float(np.sum(minus * minus))) / (2 * h)
+
+
 def test_loss_gradient_matches_central_differences():
-    """Gradient of ||S c - x||^2 + lambda ||c||_1 (ST surrogate) vs central FD, h = 1e-3."""
+    """Gradient of ||S c - x||^2 + lambda ||c||_1 (ST surrogate) vs central FD,
+    h = 1e-3, at 64 seeded coordinates, eight in each of the 8 planes."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
     from paper_1510_00561_amd import autograd as ag
     x = np.ascontiguousarray(clips.clip_planes(B5, H5, W5, 5)[0::3])   # the 8 Y planes
     plan = _plan(H5, W5, J5, D5, B5)
@@ -75,21 +103,23 @@ def test_loss_gradient_matches_central_differences():
     xd = _dev(x)
     loss = ((ag.ct_inverse(c, plan) - xd) ** 2).sum() + LAM * c.abs().sum()
     loss.backward()
-    grad = c.grad[0].double().cpu().numpy()
-    c_np = c_dev[0].double().cpu().numpy()
+    grad = c.grad.double().cpu().numpy()
+    c_np = c_dev.double().cpu().numpy()
     h = 1e-3
-
-    def L(v):
-        r = oct.inverse(v, H5, W5, J5, D5) - x[0].astype(np.float64)
-        return float(np.sum(r * r) + LAM * np.sum(np.abs(v)))
-
-    cand = np.flatnonzero(np.abs(c_np) > 10 * h)
-    picks = rng.choice(cand, size=12, replace=False)
-    for i in picks:
-        e = np.zeros_like(c_np)
-        e[i] = h
-        fd = (L(c_np + e) - L(c_np - e)) / (2 * h)
-        assert abs(grad[i] - fd) <= 1e-3 * max(abs(fd), 1.0), (i, grad[i], fd)
+    resid = np.stack([oct.inverse(c_np[b], H5, W5, J5, D5) - x[b].astype(np.float64) for b in range(B5)])
+    tasks = []
+    for b in range(B5):
+        cand = np.flatnonzero(np.abs(c_np[b]) > 10 * h)
+        for i in rng.choice(cand, size=8, replace=False):
+            tasks.append((b, int(i), h, plan.ncoef))
+    workers = max(1, min(8, (mp.cpu_count() or 1)))
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn"), initializer=_fd_init,
+                             initargs=(resid,)) as ex:
+        quad = list(ex.map(_fd_quadratic, tasks))
+    for (b, i, _, _), q in zip(tasks, quad):
+        l1 = LAM * (abs(c_np[b, i] + h) - abs(c_np[b, i] - h)) / (2 * h)
+        fd = q + l1
+        assert abs(grad[b, i] - fd) <= 1e-3 * max(abs(fd), 1.0), (b, i, grad[b, i], fd)
 
 
 def test_straight_through_quantiser_and_rd_descent():

@@ -219,3 +219,20 @@ def test_full_1080p_batch_sampled_planes():
     for b in (0, 1, 2, B - 1):
         ref = oct.forward(x[b].astype(np.float64), J, dirs)
         assert np.abs(coef_h[b] - ref).max() <= TOL, b
+    # the benchmarked codec step: fused encoder and decoder with per-subband
+    # steps; the indices are the oracle quantiser's on the GPU coefficients,
+    # and the decoder output is the oracle's inverse of the oracle's
+    # dequantisation of those indices
+    table = geo.subband_table(H, W, J, dirs)
+    steps = synth.subband_steps(plan.nsub, 3, 3)
+    steps_b = np.stack([steps[b % 3] for b in range(B)]).astype(np.float32)
+    idx, side = plan.encode(xd, _dev(steps_b))
+    dec = plan.decode(idx, _dev(steps_b), side).cpu().numpy()
+    idx_h, side_h = idx.cpu().numpy(), side.cpu().numpy()
+    for b in (1, B - 1):
+        q_ref, s_ref = oq.quantize32(coef_h[b], steps_b[b], table)
+        np.testing.assert_array_equal(idx_h[b], q_ref)
+        np.testing.assert_array_equal(side_h[b], s_ref)
+        d_ref = oq.dequantize32(q_ref, steps_b[b], s_ref, table)
+        rec_ref = oct.inverse(d_ref.astype(np.float64), H, W, J, dirs)
+        assert np.abs(dec[b] - rec_ref).max() <= TOL, b
