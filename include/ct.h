@@ -235,9 +235,9 @@ int ct_inverse_adjoint(const ct_geom* geom, int32_t batch, const float* gplanes,
  * all streams, run by one launch that covers all their tiles. The groups
  * follow in chain order on one stream. With CT_PLAN_GRAPH the group launches
  * are captured into one HIP graph. With CT_PLAN_AUTOTUNE it times, per LP
- * level shape, whether the deeper DFB tree levels stream two at a time or
- * one at a time and caches the choice in a JSON file (CT_AUTOTUNE_CACHE,
- * default $HOME/.cache/ct_autotune.json).
+ * level shape, whether the deeper DFB tree levels stream one, two or three
+ * at a time and caches the choice in a JSON file (CT_AUTOTUNE_CACHE,
+ * default $HOME/.cache/ct_autotune.json); every choice gives identical bits.
  * ct_plan_run enqueues one graph launch (or the group launches) on `stream`.
  * ct_plan_run_plain enqueues the same work as separate per-stream,
  * per-stage launches (the unbatched baseline); both give identical results.
@@ -262,7 +262,8 @@ typedef struct ct_plan ct_plan;
 typedef struct ct_plan_info_t {
     int32_t streams, stages, work_items, launches;
     int32_t graph, autotuned;
-    int32_t levels_paired, levels_single;   /* tile-shape choices of levels with l >= 4 */
+    int32_t levels_paired, levels_single;   /* LP levels with l >= 4 whose deeper tree levels run */
+    int32_t levels_triple;                  /* two, one or three per pass (the tuned choice)   */
     int64_t workspace_bytes;
 } ct_plan_info_t;
 
@@ -355,6 +356,75 @@ int ct_motion_search(int32_t batch, int32_t height, int32_t width, int32_t w, co
                      const float* prev, int16_t* mv, int32_t* ssd, hipStream_t stream);
 
 /*
+ * P-frame components (paper section 3.7): the motion-compensated prediction
+ * is made on the quantised CT components, with the luminance motion vectors
+ * of ct_motion_search mapped to each component's scale. Conventions as
+ * above; no workspace.
+ *   cur, prev   int16 [batch][ncoef] indices of the current and previous
+ *               frames (ct_quantize / ct_encode layout).
+ *   mv, nby,    int16 [ceil(batch / mv_group)][nby][nbx][2] block vectors
+ *   nbx,        (dy, dx) of ct_motion_search; plane b uses field
+ *   mv_group    b / mv_group (3 for the Y, Co, Cg planes of one frame).
+ *   n           chroma subsampling factor of the planes (1 for luminance).
+ * A sample (i, k) of a subband of level j with lattice offset (o1, o2) and
+ * steps (s1, s2) (ct_subband) sits at luminance pixel
+ * n 2^(j-1) (o1 + s1 i, o2 + s2 k), a lowpass sample at n 2^J (i, k); it
+ * takes the vector of the 16 x 16 block holding that pixel (the last block
+ * row / column for the padding), divided by its sample spacing n 2^(j-1)
+ * (s1, s2) (n 2^J for the lowpass) and rounded to the nearest integer,
+ * halves away from zero. The prediction is the previous plane's component
+ * at the displaced position in its natural orientation, modulo the
+ * component's size.
+ *   inverse = 0   out = cur - prediction (encoder)
+ *   inverse != 0  out = cur + prediction (decoder: cur holds the P-frame
+ *                 components, out the frame's indices)
+ * Arithmetic modulo 2^16, so the pair is exact on any input. out may be cur
+ * (in place), not prev.
+ */
+int ct_mc_residual(const ct_geom* geom, int32_t batch, int32_t n, const int16_t* cur,
+                   const int16_t* prev, const int16_t* mv, int32_t nby, int32_t nbx,
+                   int32_t mv_group, int32_t inverse, int16_t* out, hipStream_t stream);
+
+/*
+ * Zero-run coding (paper section 3.8) of quantised indices, on the device.
+ * Every component is read along its natural rows (image rows; the
+ * transposed vertical-cone subbands along their stored columns). In a coded
+ * component a non-zero value is one int16 symbol, itself, and a maximal run
+ * of n zeros inside a row is the two symbols 0, n. K-frames (p_frame = 0)
+ * code the directional subbands and copy the lowpass unchanged; P-frames
+ * (p_frame != 0) code every component.
+ *   idx       int16 [batch][ncoef] input.
+ *   symbols   int16 [batch][2 ncoef] output; plane b's stream starts at
+ *             symbols + b 2 ncoef (2 ncoef bounds any stream).
+ *   sub_off   int32 [batch][nsub + 1] output: the symbol offset of every
+ *             component within its plane's stream, then the plane's count.
+ *   ws        workspace of ct_rle_workspace_bytes() bytes.
+ * ct_rle_decode_host is the decoder (host code, one plane, host pointers):
+ * it parses every component's rows and returns CT_ERR_ARG for a stream
+ * that does not parse to exactly the layout.
+ */
+int ct_rle_workspace_bytes(const ct_geom* geom, int32_t batch, size_t* bytes);
+int ct_rle_encode(const ct_geom* geom, int32_t batch, const int16_t* idx, int32_t p_frame,
+                  int16_t* symbols, int32_t* sub_off, void* ws, size_t ws_bytes, hipStream_t stream);
+int ct_rle_decode_host(const ct_geom* geom, const int16_t* symbols, const int32_t* sub_off,
+                       int32_t p_frame, int16_t* idx);
+
+/*
+ * DEFLATE of one plane's symbol stream (paper section 3.9), host code
+ * (zlib, compression level 0..9). mode 0 compresses every component on its
+ * own (transmission scalability: comp_bytes[s] for each of the nsub
+ * components, back to back in out); mode 1 compresses the whole plane at
+ * once (CVC-NTS: comp_bytes[0]). The symbols are taken as little-endian
+ * int16 bytes. *total receives the bytes written; CT_ERR_WORKSPACE if cap
+ * is too small (cap = sum of compressBound over the parts always suffices).
+ * ct_inflate_host is the inverse; it needs sub_off to size every part.
+ */
+int ct_deflate_host(const int16_t* symbols, const int32_t* sub_off, int32_t nsub, int32_t mode,
+                    int32_t level, uint8_t* out, size_t cap, uint32_t* comp_bytes, size_t* total);
+int ct_inflate_host(const uint8_t* in, const uint32_t* comp_bytes, const int32_t* sub_off,
+                    int32_t nsub, int32_t mode, int16_t* symbols);
+
+/*
  * Per-kernel timing (HIP events), for benchmarks and tracing.
  * ct_profile_enable(1) creates a pool of `max_launches` event pairs (0 picks
  * 16384) and makes every later launch record one event before and one after
@@ -363,7 +433,10 @@ int ct_motion_search(int32_t batch, int32_t height, int32_t width, int32_t w, co
  * nothing on the device.
  * ct_profile_collect waits for the recorded events, aggregates them by
  * kernel (name, launches, total milliseconds, compulsory bytes = inputs read
- * once + outputs written once), writes up to `cap` entries, sets *n to the
+ * once + outputs written once, and alg_bytes = the part of those that are the
+ * codec's own inputs and outputs: frames, float coefficients when the call
+ * writes or reads them, indices; workspace intermediates excluded), writes
+ * up to `cap` entries, sets *n to the
  * number of kernels seen, and clears the record. Returns CT_ERR_HIP if an
  * event query fails, CT_ERR_UNSUPPORTED if launches were dropped because
  * the pool ran out.
@@ -373,6 +446,7 @@ typedef struct ct_kernel_stat {
     int64_t launches;
     double total_ms;
     double bytes;
+    double alg_bytes;
 } ct_kernel_stat;
 int ct_profile_enable(int32_t on, int32_t max_launches);
 int ct_profile_collect(ct_kernel_stat* out, int32_t cap, int32_t* n);

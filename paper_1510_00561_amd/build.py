@@ -29,6 +29,8 @@ SOURCES = [
     ("ct_motion_api.cpp", []),
     ("ct_motion.hip", []),
     ("ct_noalloc.hip", []),
+    ("ct_codec_api.cpp", []),
+    ("ct_codec.hip", []),
 ]
 
 COMMON = [
@@ -63,7 +65,7 @@ def build(verbose=False):
     with ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(lambda s: _compile(*s), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + ["-lz"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

@@ -89,7 +89,7 @@ namespace ct {
 // created by ct_profile_enable so that recording never allocates.
 struct ProfRecord {
     const char* name;
-    double bytes;
+    double bytes, alg;
     hipEvent_t a, b;
 };
 struct Profiler {
@@ -105,7 +105,7 @@ static Profiler& profiler() {
     return p;
 }
 
-ProfScope::ProfScope(const char* n, double by, hipStream_t s) : name(n), bytes(by), st(s) {
+ProfScope::ProfScope(const char* n, double by, double al, hipStream_t s) : name(n), bytes(by), alg(al), st(s) {
     Profiler& p = profiler();
     std::lock_guard<std::mutex> lock(p.mu);
     if (!p.on) return;
@@ -123,7 +123,7 @@ void ProfScope::done() {
     Profiler& p = profiler();
     std::lock_guard<std::mutex> lock(p.mu);
     hipEventRecord(b, st);
-    p.recs.push_back(ProfRecord{name, bytes, a, b});
+    p.recs.push_back(ProfRecord{name, bytes, alg, a, b});
 }
 
 }  // namespace ct
@@ -136,13 +136,13 @@ int check_common(const ct_geom* geom, int32_t batch, Geometry* g) {
     return resolve(geom, g);
 }
 
-// Groups of DFB tree levels >= 3 run per pass. grouping 2: pairs from the
-// top, then a single trailing level when their count is odd; grouping 1:
-// one level per pass.
+// Groups of DFB tree levels >= 3 run per pass: `grouping` (1, 2 or 3)
+// levels per pass from the top, and the remaining levels in a last, shorter
+// pass.
 int split_groups(int l, int grouping, int* first, int* count) {
     int n = 0;
     for (int t = 3; t <= l;) {
-        const int c = (grouping == 2 && t + 1 <= l) ? 2 : 1;
+        const int c = t + grouping - 1 <= l ? grouping : l - t + 1;
         first[n] = t;
         count[n] = c;
         ++n;
@@ -190,7 +190,18 @@ int split_block_rows(const SplitArgs& a, int batch, int levels) {
     // one-level passes carry a small halo and few instructions per row: they
     // run fastest with shorter blocks and four times as many wavefronts
     const int slots = levels == 1 ? 4 * resident_waves() : resident_waves();
-    return block_rows(nrh > nrv ? nrh : nrv, cols, slots, 32, stream_max_rows(levels), 4);
+    return block_rows(nrh > nrv ? nrh : nrv, cols, slots, 32, stream_max_rows(levels),
+                      stream_row_align(levels));
+}
+
+// Stage type of a split pass over `levels` tree levels.
+static int split_type(int levels, bool analysis, bool quant) {
+    static const int ana[3] = {kStSplit1Ana, kStSplit2Ana, kStSplit3Ana};
+    static const int anaq[3] = {kStSplit1AnaQ, kStSplit2AnaQ, kStSplit3AnaQ};
+    static const int syn[3] = {kStSplit1Syn, kStSplit2Syn, kStSplit3Syn};
+    static const int synq[3] = {kStSplit1SynQ, kStSplit2SynQ, kStSplit3SynQ};
+    const int i = levels - 1;
+    return analysis ? (quant ? anaq[i] : ana[i]) : (quant ? synq[i] : syn[i]);
 }
 
 // Subband index of the first subband of LP level j in the coefficient layout
@@ -281,6 +292,11 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
             const double chan = l == 2 ? (level ? 4.0 : 0.0) + (qio.idx ? 2.0 : 0.0) : 4.0;
             d.bytes = batch * (4.0 * double(a.src_h) * a.src_w + 4.0 * double(Rj / 2) * (Cj / 2) +
                                chan * double(Rj) * Cj);
+            // algorithmic: the frame (level 1), the float lowpass when it is
+            // the caller's output, the final subbands when this stage makes them
+            d.alg = batch * ((j == 1 ? 4.0 * double(a.src_h) * a.src_w : 0.0) +
+                             (j == g.J && coeffs ? 4.0 * double(Rj / 2) * (Cj / 2) : 0.0) +
+                             (l == 2 ? chan * double(Rj) * Cj : 0.0));
             push(d);
             int first[4], count[4];
             const int ng = split_groups(l, grouping[j - 1], first, count);
@@ -290,7 +306,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                 const bool last = gi == ng - 1;
                 StageDesc e;
                 memset(&e, 0, sizeof(e));
-                e.type = count[gi] == 2 ? kStSplit2Ana : kStSplit1Ana;
+                e.type = split_type(count[gi], true, false);
                 SplitArgs& sa = e.u.sp;
                 sa.t = first[gi];
                 sa.Rj = Rj;
@@ -304,7 +320,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     sa.use_scale = 1;
                     memcpy(sa.scale, sc, sizeof(float) * (1 << l));
                     sa.q = qio;
-                    if (qio.idx) e.type = count[gi] == 2 ? kStSplit2AnaQ : kStSplit1AnaQ;
+                    if (qio.idx) e.type = split_type(count[gi], true, true);
                 } else {
                     sa.child = other;
                     sa.child_plane = RC;
@@ -313,6 +329,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                 e.ntiles = split_stage_tiles(sa, batch, count[gi]);
                 const double out_b = last ? (level ? 4.0 : 0.0) + (qio.idx ? 2.0 : 0.0) : 4.0;
                 e.bytes = batch * (4.0 + out_b) * double(Rj) * Cj;
+                e.alg = last ? batch * out_b * double(Rj) * Cj : 0.0;
                 push(e);
                 float* tmp = cur;
                 cur = other;
@@ -352,7 +369,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
             for (int gi = ng - 1; gi >= 0; --gi) {
                 StageDesc e;
                 memset(&e, 0, sizeof(e));
-                e.type = count[gi] == 2 ? kStSplit2Syn : kStSplit1Syn;
+                e.type = split_type(count[gi], false, false);
                 SplitArgs& sa = e.u.sp;
                 sa.t = first[gi];
                 sa.Rj = Rj;
@@ -366,7 +383,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     sa.use_scale = 1;
                     memcpy(sa.scale, sc, sizeof(float) * (1 << l));
                     sa.q = qio;
-                    if (qio.idx) e.type = count[gi] == 2 ? kStSplit2SynQ : kStSplit1SynQ;
+                    if (qio.idx) e.type = split_type(count[gi], false, true);
                 } else {
                     sa.parent = other;
                     sa.parent_plane = RC;
@@ -375,6 +392,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                 e.ntiles = split_stage_tiles(sa, batch, count[gi]);
                 const double in_b = (gi == ng - 1 && qio.idx) ? 2.0 : 4.0;
                 e.bytes = batch * (in_b + 4.0) * double(Rj) * Cj;
+                e.alg = gi == ng - 1 ? batch * in_b * double(Rj) * Cj : 0.0;
                 push(e);
                 float* tmp = cur;
                 cur = other;
@@ -418,6 +436,11 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
         const double ch_b = (l == 2 && fq) ? 2.0 : 4.0;
         d.bytes = batch * (c_b * double(Rj / 2) * (Cj / 2) + ch_b * double(Rj) * Cj +
                            4.0 * double(a.out_h) * a.out_w);
+        // algorithmic: the lowpass (coarsest level), the final subbands when
+        // this stage reads them, the frame (level 1)
+        d.alg = batch * ((j == g.J ? c_b * double(Rj / 2) * (Cj / 2) : 0.0) +
+                         (l == 2 ? ch_b * double(Rj) * Cj : 0.0) +
+                         (j == 1 ? 4.0 * double(a.out_h) * a.out_w : 0.0));
         push(d);
     }
 }
@@ -434,6 +457,10 @@ const char* stage_name(int type) {
         case kStSplit1AnaQ: return "dfb_split_analysis";
         case kStSplit2Ana:
         case kStSplit2AnaQ: return "dfb_split2_analysis";
+        case kStSplit3Ana:
+        case kStSplit3AnaQ: return "dfb_split3_analysis";
+        case kStSplit3Syn:
+        case kStSplit3SynQ: return "dfb_split3_synthesis";
         case kStPartial: return "lowpass_partial";
         case kStQuantize: return "quantize";
         case kStDequantize: return "dequantize";
@@ -461,6 +488,10 @@ hipError_t launch_stage_raw(const StageDesc& d, hipStream_t st) {
         case kStSplit1SynQ: return launch_dfb_split_synthesis(d.u.sp, d.lift, d.batch, st);
         case kStSplit2Syn:
         case kStSplit2SynQ: return launch_dfb_split2_synthesis(d.u.sp, d.lift, d.batch, st);
+        case kStSplit3Ana:
+        case kStSplit3AnaQ: return launch_dfb_split3_analysis(d.u.sp, d.lift, d.batch, st);
+        case kStSplit3Syn:
+        case kStSplit3SynQ: return launch_dfb_split3_synthesis(d.u.sp, d.lift, d.batch, st);
         case kStPartial: return launch_lowpass_partial(d.u.q, d.batch, st);
         case kStQuantize: return launch_quantize(d.u.q, d.batch, st);
         case kStDequantize: return launch_dequantize(d.u.q, d.batch, st);
@@ -473,7 +504,7 @@ hipError_t launch_stage_raw(const StageDesc& d, hipStream_t st) {
 namespace ct {
 
 int launch_stage(const StageDesc& d, hipStream_t st) {
-    CT_PROFILED(stage_name(d.type), d.bytes, launch_stage_raw(d, st), st);
+    CT_PROFILED_ALG(stage_name(d.type), d.bytes, d.alg, launch_stage_raw(d, st), st);
     return CT_OK;
 }
 
@@ -489,7 +520,7 @@ int launch_chain(const std::vector<StageDesc>& chain, hipStream_t st) {
 
 namespace {
 
-const int kDefaultGrouping[kMaxLevels] = {2, 2, 2, 2, 2, 2};
+const int kDefaultGrouping[kMaxLevels] = {3, 3, 3, 3, 3, 3};
 
 int transform(const ct_geom* geom, int32_t batch, const float* in, float* out, void* ws,
               size_t ws_bytes, hipStream_t st, Mode mode) {
@@ -562,10 +593,12 @@ int build_quant_chain(const Geometry& g, int batch, const float* coeffs, const f
     d.type = kStPartial;
     d.ntiles = a.nparts * batch;
     d.bytes = 4.0 * batch * double(g.low_n);
+    d.alg = 0.0;                            // the lowpass is read again by the next pass
     chain.push_back(d);
     d.type = kStQuantize;
     d.ntiles = int((g.ncoef + 4095) / 4096) * batch;
     d.bytes = 6.0 * batch * double(g.ncoef);
+    d.alg = d.bytes;
     chain.push_back(d);
     return CT_OK;
 }
@@ -591,10 +624,13 @@ int build_lowpass_quant_chain(const Geometry& g, int batch, const float* low, in
     d.type = kStPartial;
     d.ntiles = a.nparts * batch;
     d.bytes = 4.0 * batch * double(g.low_n);
+    d.alg = 0.0;
     chain.push_back(d);
     d.type = kStQuantize;
     d.ntiles = int((g.low_n + 4095) / 4096) * batch;
     d.bytes = 6.0 * batch * double(g.low_n);
+    // the float lowpass is the caller's output only when it sits in coeffs
+    d.alg = (low_plane == g.ncoef ? 6.0 : 2.0) * batch * double(g.low_n);
     chain.push_back(d);
     return CT_OK;
 }
@@ -617,6 +653,7 @@ int build_dequant_chain(const Geometry& g, int batch, const int16_t* idx, const 
     d.type = kStDequantize;
     d.ntiles = int((g.ncoef + 4095) / 4096) * batch;
     d.bytes = 6.0 * batch * double(g.ncoef);
+    d.alg = d.bytes;
     chain.push_back(d);
     return CT_OK;
 }
@@ -839,6 +876,7 @@ int ct_profile_collect(ct_kernel_stat* out, int32_t cap, int32_t* n) {
         it->second.launches += 1;
         it->second.total_ms += ms;
         it->second.bytes += r.bytes;
+        it->second.alg_bytes += r.alg;
     }
     *n = int32_t(order.size());
     for (int32_t i = 0; i < cap && i < int32_t(order.size()); ++i) out[i] = agg[order[i]];

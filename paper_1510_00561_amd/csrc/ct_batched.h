@@ -32,7 +32,12 @@ enum StageType : int {
     kStSplit1SynQ = 12,
     kStSplit2SynQ = 13,
     kStLevelSynQ = 14,
-    kStNumTypes = 15,
+    // three DFB tree levels per pass, plain and with quantised final subbands
+    kStSplit3Ana = 15,
+    kStSplit3Syn = 16,
+    kStSplit3AnaQ = 17,
+    kStSplit3SynQ = 18,
+    kStNumTypes = 19,
 };
 
 struct StageDesc {
@@ -40,7 +45,9 @@ struct StageDesc {
     int ntiles;
     int batch;
     int lo_r;            // reach of the LP `lo` filter: 4 (hbar) or 3 (gbar, transposes)
-    double bytes;        // compulsory bytes (profiling)
+    double bytes;        // compulsory bytes (profiling): every array read once, written once
+    double alg;          // of these, the codec's own inputs and outputs (frames, float
+                         // coefficients, indices): the algorithmic bytes
     Lift lift;
     union {
         stage::LevelAnaArgs la;

@@ -1,7 +1,9 @@
 // Group kernels of the batched form (gfx950).
 //
 // One launch runs the stages of one type at one chain position of every
-// stream of a plan: a workgroup finds its stage among the group's stages by
+// stream of a plan (forward and inverse transforms only: the split stages run
+// the forward lifting, first_odd = 1, in the analysis and the inverse one,
+// first_odd = 0, in the synthesis): a workgroup finds its stage among the group's stages by
 // binary search over their first tiles and runs that tile with the same
 // stage code as the per-stage kernels. There is no communication between
 // workgroups; the launches of a plan follow each other in chain order on
@@ -21,6 +23,12 @@ using S1A = stream::StreamSplit<1, true, NT>;
 using S2A = stream::StreamSplit<2, true, NT>;
 using S1S = stream::StreamSplit<1, false, NT>;
 using S2S = stream::StreamSplit<2, false, NT>;
+using S3A = stream::StreamSplit<3, true, NT>;
+using S3S = stream::StreamSplit<3, false, NT>;
+
+constexpr bool quantised(int type) {
+    return (type >= kStLevelAnaQ && type <= kStLevelSynQ) || type == kStSplit3AnaQ || type == kStSplit3SynQ;
+}
 
 __device__ __forceinline__ int find_stage(const int* first, int n, int tile) {
     int lo = 0, hi = n - 1;                  // largest s with first[s] <= tile
@@ -53,7 +61,7 @@ __global__ __launch_bounds__(NT, TYPE == kStLevelAna ? 4 : 1) void group_kernel(
     const int s = find_stage(first, n, t);
     const int tile = t - first[s];
     const StageDesc& d = stages[s];
-    constexpr bool Q = TYPE >= kStLevelAnaQ;
+    constexpr bool Q = quantised(TYPE);
     if constexpr (TYPE == kStLevelAna || TYPE == kStLevelAnaQ) {
         LA st(d.u.la);
         st.template run_tile<Q>(tile, smem);
@@ -62,16 +70,22 @@ __global__ __launch_bounds__(NT, TYPE == kStLevelAna ? 4 : 1) void group_kernel(
         st.template run_tile<Q>(tile, smem);
     } else if constexpr (TYPE == kStSplit1Ana || TYPE == kStSplit1AnaQ) {
         S1A st(d.u.sp, d.batch, d.lift);
-        st.template run_tile<Q>(tile);
+        st.template run_tile<Q, 1>(tile);
     } else if constexpr (TYPE == kStSplit2Ana || TYPE == kStSplit2AnaQ) {
         S2A st(d.u.sp, d.batch, d.lift);
-        st.template run_tile<Q>(tile);
+        st.template run_tile<Q, 1>(tile);
+    } else if constexpr (TYPE == kStSplit3Ana || TYPE == kStSplit3AnaQ) {
+        S3A st(d.u.sp, d.batch, d.lift);
+        st.template run_tile<Q, 1>(tile);
+    } else if constexpr (TYPE == kStSplit3Syn || TYPE == kStSplit3SynQ) {
+        S3S st(d.u.sp, d.batch, d.lift);
+        st.template run_tile<Q, 0>(tile);
     } else if constexpr (TYPE == kStSplit1Syn || TYPE == kStSplit1SynQ) {
         S1S st(d.u.sp, d.batch, d.lift);
-        st.template run_tile<Q>(tile);
+        st.template run_tile<Q, 0>(tile);
     } else if constexpr (TYPE == kStSplit2Syn || TYPE == kStSplit2SynQ) {
         S2S st(d.u.sp, d.batch, d.lift);
-        st.template run_tile<Q>(tile);
+        st.template run_tile<Q, 0>(tile);
     } else if constexpr (TYPE == kStPartial) {
         qstage::lowpass_partial<NT>(d.u.q, tile, smem);
     } else if constexpr (TYPE == kStQuantize) {
@@ -108,6 +122,10 @@ hipError_t launch_group(int type, const StageDesc* stages, const int* first, int
         case kStSplit2AnaQ: return launch_type<kStSplit2AnaQ>(stages, first, n, tiles, st);
         case kStSplit1SynQ: return launch_type<kStSplit1SynQ>(stages, first, n, tiles, st);
         case kStSplit2SynQ: return launch_type<kStSplit2SynQ>(stages, first, n, tiles, st);
+        case kStSplit3Ana: return launch_type<kStSplit3Ana>(stages, first, n, tiles, st);
+        case kStSplit3Syn: return launch_type<kStSplit3Syn>(stages, first, n, tiles, st);
+        case kStSplit3AnaQ: return launch_type<kStSplit3AnaQ>(stages, first, n, tiles, st);
+        case kStSplit3SynQ: return launch_type<kStSplit3SynQ>(stages, first, n, tiles, st);
         default: return hipErrorInvalidValue;
     }
 }

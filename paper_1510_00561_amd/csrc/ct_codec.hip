@@ -1,0 +1,396 @@
+// P-frame motion compensation (paper section 3.7) and zero-run coding
+// (section 3.8) of the quantised CT components, for gfx950.
+//
+// Motion compensation is one pass over the indices: every element finds its
+// component and natural position (i, k), the 16 x 16 block of the luminance
+// pixel it sits on, that block's vector mapped to the component's sample
+// spacing (rounded, halves away from zero), and subtracts (or, for the
+// decoder, adds) the previous plane's element at the displaced position,
+// modulo the component's size and modulo 2^16. HBM-bound: 2 bytes read,
+// 2 gathered (mostly within the lines of the same row) and 2 written per
+// element.
+//
+// The zero-run coder is a stream compaction in three passes:
+//   1. symbols per natural row: rows stored contiguously (the lowpass, the
+//      horizontal-cone subbands) take one wavefront each, lanes along the
+//      row; rows of the transposed vertical-cone subbands are stored
+//      columns, so one wavefront takes 64 of them, one per lane, and walks
+//      down the stored rows with coalesced loads;
+//   2. per plane, an exclusive scan of the row counts (one workgroup per
+//      plane) gives every row's symbol offset and every component's offset;
+//   3. symbols: the same decomposition as pass 1. Within a wavefront, a
+//      row's symbol positions come from a prefix sum of the per-element
+//      symbol counts (1 for a non-zero value, 2 for the first zero of a run),
+//      and the element that ends a run writes its length next to the run's
+//      0, found from a prefix maximum of the last non-zero position.
+#include "ct_codec.h"
+
+namespace ct {
+namespace codec {
+namespace {
+
+constexpr int NT = 256;
+
+__device__ __forceinline__ int pmod(int a, int n) {
+    const int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// a / b rounded to the nearest integer, halves away from zero (b > 0)
+__device__ __forceinline__ int round_div(int a, int b) {
+    const int q = (2 * abs(a) + b) / (2 * b);
+    return a < 0 ? -q : q;
+}
+
+// Storage position p (0 = lowpass, then levels J..1) -> level index (0 =
+// lowpass, else the LP level j).
+__device__ __forceinline__ int level_of_pos(const LevelTable& T, int p) { return p == 0 ? 0 : T.J + 1 - p; }
+
+__device__ __forceinline__ int find_pos(const LevelTable& T, int64_t e) {
+    int p = 0;
+    while (p < T.J && e >= T.off[p + 1]) ++p;
+    return p;
+}
+
+__global__ __launch_bounds__(NT) void mc_kernel(MCArgs A) {
+    const LevelTable& T = A.T;
+    const int64_t gid = int64_t(blockIdx.x) * NT + threadIdx.x;
+    if (gid >= int64_t(A.batch) * T.ncoef) return;
+    const int b = int(gid / T.ncoef);
+    const int64_t e = gid - int64_t(b) * T.ncoef;
+    const int p = find_pos(T, e);
+    const int lv = level_of_pos(T, p);
+    const int local = int(e - T.off[p]);
+    int i, k, rows, cols, py, px, sy, sx;
+    bool tr = false;
+    int64_t base = T.off[p];
+    if (lv == 0) {
+        rows = T.R >> T.J;
+        cols = T.C >> T.J;
+        i = local / cols;
+        k = local - i * cols;
+        sy = sx = A.n << T.J;
+        py = sy * i;
+        px = sx * k;
+    } else {
+        const int sz = T.rows_h[lv] * T.cols_h[lv];
+        const int kk = local / sz, w = local - kk * sz;
+        const int f = A.n << (lv - 1);
+        int s1, s2;
+        if (kk < T.nh[lv]) {
+            rows = T.rows_h[lv];
+            cols = T.cols_h[lv];
+            i = w / cols;
+            k = w - i * cols;
+            s1 = 1 << T.lsh1_h[lv];
+            s2 = 1 << T.lsh2_h[lv];
+        } else {
+            rows = T.rows_v[lv];
+            cols = T.cols_v[lv];
+            k = w / rows;
+            i = w - k * rows;
+            tr = true;
+            s1 = 1 << T.lsh1_v[lv];
+            s2 = 1 << T.lsh2_v[lv];
+        }
+        base += int64_t(kk) * sz;
+        py = f * (T.o1[lv][kk] + s1 * i);
+        px = f * (T.o2[lv][kk] + s2 * k);
+        sy = f * s1;
+        sx = f * s2;
+    }
+    const int by = min(py >> 4, A.nby - 1), bx = min(px >> 4, A.nbx - 1);
+    const int16_t* v = A.mv + ((int64_t(b / A.group) * A.nby + by) * A.nbx + bx) * 2;
+    const int i2 = pmod(i + round_div(v[0], sy), rows);
+    const int k2 = pmod(k + round_div(v[1], sx), cols);
+    const int64_t src = base + (tr ? int64_t(k2) * rows + i2 : int64_t(i2) * cols + k2);
+    const int pv = A.prev[int64_t(b) * T.ncoef + src];
+    const int cv = A.cur[gid];
+    A.out[gid] = int16_t(A.inverse ? cv + pv : cv - pv);   // modulo 2^16
+}
+
+// ---------------------------------------------------------------- zero runs
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ int wave_incl_sum(int v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_incl_max(int v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v = max(v, t);
+    }
+    return v;
+}
+
+// What one wavefront item of a plane covers.
+struct Item {
+    bool valid;
+    bool contiguous;     // one row, lanes along it; else up to 64 transposed rows, one per lane
+    bool coded;          // zero runs coded (else the row is copied unchanged)
+    int64_t start;       // element offset (within the plane) of the row, or of the stored block
+    int len;             // row length (contiguous) / natural row length (transposed)
+    int rows_v;          // transposed: natural rows of the subband (stored row stride)
+    int i0;              // transposed: first natural row of the item
+    int row;             // row id of the (first) natural row
+};
+
+// Items of storage position p: the lowpass rows; or, for a level, nh * rows_h
+// contiguous rows, then (nsub - nh) * ceil(rows_v / 64) transposed groups.
+__device__ Item item_of(const LevelTable& T, const int* item0, int it, int p_frame) {
+    Item r;
+    r.valid = false;
+    int p = 0;
+    while (p <= T.J && it >= item0[p + 1]) ++p;
+    if (p > T.J) return r;
+    r.valid = true;
+    const int lv = level_of_pos(T, p);
+    int w = it - item0[p];
+    if (lv == 0) {
+        const int cols = T.C >> T.J;
+        r.contiguous = true;
+        r.coded = p_frame != 0;
+        r.start = int64_t(w) * cols;
+        r.len = cols;
+        r.row = T.row0[p] + w;
+        return r;
+    }
+    r.coded = true;
+    const int sz = T.rows_h[lv] * T.cols_h[lv];
+    const int nhr = T.nh[lv] * T.rows_h[lv];
+    if (w < nhr) {
+        r.contiguous = true;
+        const int kk = w / T.rows_h[lv], i = w - kk * T.rows_h[lv];
+        r.start = T.off[p] + int64_t(kk) * sz + int64_t(i) * T.cols_h[lv];
+        r.len = T.cols_h[lv];
+        r.row = T.row0[p] + w;
+        return r;
+    }
+    w -= nhr;
+    const int groups = (T.rows_v[lv] + 63) / 64;
+    const int kv = w / groups, g = w - kv * groups;
+    r.contiguous = false;
+    r.start = T.off[p] + int64_t(T.nh[lv] + kv) * sz;
+    r.len = T.cols_v[lv];
+    r.rows_v = T.rows_v[lv];
+    r.i0 = 64 * g;
+    r.row = T.row0[p] + nhr + kv * T.rows_v[lv] + r.i0;
+    return r;
+}
+
+struct ItemTable {
+    int item0[kMaxLevels + 3];
+};
+
+__global__ __launch_bounds__(NT) void rle_count_kernel(RLEArgs A, ItemTable IT) {
+    const LevelTable& T = A.T;
+    const int per = IT.item0[T.J + 1];
+    const int gw = int(blockIdx.x) * (NT / 64) + int(threadIdx.x >> 6);
+    if (gw >= per * A.batch) return;
+    const int b = gw / per;
+    const Item m = item_of(T, IT.item0, gw - b * per, A.p_frame);
+    if (!m.valid) return;
+    const int lane = lane_id();
+    const int16_t* x = A.idx + int64_t(b) * T.ncoef + m.start;
+    int32_t* cnt = A.rowcnt + int64_t(b) * A.nrows;
+    if (m.contiguous) {
+        int c = 0;
+        if (!m.coded) {
+            c = m.len;
+        } else {
+            int carry = 1;                         // before the row: "non-zero"
+            for (int c0 = 0; c0 < m.len; c0 += 64) {
+                const int e = c0 + lane;
+                const bool in = e < m.len;
+                const int v = in ? x[e] : 1;
+                const int up = __shfl_up(v, 1, 64);
+                const int pv = lane == 0 ? carry : up;
+                c += in ? (v != 0 ? 1 : (pv != 0 ? 2 : 0)) : 0;
+                carry = __shfl(v, 63, 64);
+            }
+            c = wave_incl_sum(c);
+            c = __shfl(c, 63, 64);
+        }
+        if (lane == 0) cnt[m.row] = c;
+    } else {
+        const int i = m.i0 + lane;
+        if (i < m.rows_v) {
+            int c = 0;
+            bool pnz = true;
+            for (int r = 0; r < m.len; ++r) {
+                const int v = x[int64_t(r) * m.rows_v + i];
+                c += v != 0 ? 1 : (pnz ? 2 : 0);
+                pnz = v != 0;
+            }
+            cnt[m.row + lane] = c;
+        }
+    }
+}
+
+// One workgroup per plane: exclusive scan of the plane's row counts, and the
+// symbol offset of every component.
+constexpr int SCAN_NT = 1024;
+__global__ __launch_bounds__(SCAN_NT) void rle_scan_kernel(RLEArgs A) {
+    __shared__ int part[SCAN_NT / 64];
+    __shared__ int tot;
+    const LevelTable& T = A.T;
+    const int b = blockIdx.x;
+    const int32_t* cnt = A.rowcnt + int64_t(b) * A.nrows;
+    int32_t* off = A.rowoff + int64_t(b) * A.nrows;
+    const int chunk = (A.nrows + SCAN_NT - 1) / SCAN_NT;
+    const int r0 = min(A.nrows, int(threadIdx.x) * chunk), r1 = min(A.nrows, r0 + chunk);
+    int s = 0;
+    for (int r = r0; r < r1; ++r) s += cnt[r];
+    const int incl = wave_incl_sum(s);
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 63) part[wv] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wv; ++w) before += part[w];
+    if (threadIdx.x == SCAN_NT - 1) tot = before + incl;
+    int run = before + incl - s;
+    for (int r = r0; r < r1; ++r) {
+        off[r] = run;
+        run += cnt[r];
+    }
+    __syncthreads();
+    // component offsets: component s is subband k of storage position p
+    int32_t* so = A.sub_off + int64_t(b) * (A.nsub + 1);
+    for (int sb = threadIdx.x; sb < A.nsub; sb += SCAN_NT) {
+        int p = 0;
+        while (p < T.J && sb >= T.sub0[level_of_pos(T, p + 1)]) ++p;
+        const int lv = level_of_pos(T, p);
+        const int k = sb - T.sub0[lv];
+        int row = T.row0[p];
+        if (lv > 0) row += k < T.nh[lv] ? k * T.rows_h[lv] : T.nh[lv] * T.rows_h[lv] + (k - T.nh[lv]) * T.rows_v[lv];
+        so[sb] = row < A.nrows ? off[row] : tot;
+    }
+    if (threadIdx.x == 0) so[A.nsub] = tot;
+}
+
+__global__ __launch_bounds__(NT) void rle_write_kernel(RLEArgs A, ItemTable IT) {
+    const LevelTable& T = A.T;
+    const int per = IT.item0[T.J + 1];
+    const int gw = int(blockIdx.x) * (NT / 64) + int(threadIdx.x >> 6);
+    if (gw >= per * A.batch) return;
+    const int b = gw / per;
+    const Item m = item_of(T, IT.item0, gw - b * per, A.p_frame);
+    if (!m.valid) return;
+    const int lane = lane_id();
+    const int16_t* x = A.idx + int64_t(b) * T.ncoef + m.start;
+    const int32_t* off = A.rowoff + int64_t(b) * A.nrows;
+    int16_t* out = A.sym + int64_t(b) * 2 * T.ncoef;
+    if (m.contiguous) {
+        int pos = off[m.row];
+        if (!m.coded) {
+            for (int e = lane; e < m.len; e += 64) out[pos + e] = x[e];
+            return;
+        }
+        int carry = 1;            // previous element (before the row: non-zero)
+        int lastnz = -1;          // last non-zero position before the chunk
+        for (int c0 = 0; c0 < m.len; c0 += 64) {
+            const int e = c0 + lane;
+            const bool in = e < m.len;
+            const int v = in ? x[e] : 1;
+            const int up = __shfl_up(v, 1, 64);
+            const int dn = __shfl_down(v, 1, 64);
+            const int pv = lane == 0 ? carry : up;
+            const int nv = lane == 63 ? (e + 1 < m.len ? int(x[e + 1]) : 1) : (e + 1 < m.len ? dn : 1);
+            const int s = in ? (v != 0 ? 1 : (pv != 0 ? 2 : 0)) : 0;
+            const int incl = wave_incl_sum(s);
+            const int p = pos + incl - s;
+            const int nz = max(lastnz, wave_incl_max(in && v != 0 ? e : -1));
+            if (in) {
+                if (v != 0) {
+                    out[p] = int16_t(v);
+                } else {
+                    if (pv != 0) out[p] = 0;                 // a run starts here
+                    if (nv != 0) {                           // and ends here
+                        const int start = nz + 1;
+                        out[start == e ? p + 1 : p - 1] = int16_t(e - start + 1);
+                    }
+                }
+            }
+            pos += __shfl(incl, 63, 64);
+            carry = __shfl(v, 63, 64);
+            lastnz = __shfl(nz, 63, 64);
+        }
+    } else {
+        const int i = m.i0 + lane;
+        if (i >= m.rows_v) return;
+        int pos = off[m.row + lane];
+        bool in_run = false;
+        int run_tok = 0, run_len = 0;
+        for (int r = 0; r < m.len; ++r) {
+            const int v = x[int64_t(r) * m.rows_v + i];
+            if (v != 0) {
+                if (in_run) {
+                    out[run_tok + 1] = int16_t(run_len);
+                    in_run = false;
+                }
+                out[pos++] = int16_t(v);
+            } else {
+                if (!in_run) {
+                    in_run = true;
+                    run_tok = pos;
+                    out[pos] = 0;
+                    pos += 2;
+                    run_len = 0;
+                }
+                ++run_len;
+            }
+        }
+        if (in_run) out[run_tok + 1] = int16_t(run_len);
+    }
+}
+
+ItemTable items_of(const LevelTable& T) {
+    ItemTable it;
+    it.item0[0] = 0;
+    for (int p = 0; p <= T.J; ++p) {
+        const int lv = p == 0 ? 0 : T.J + 1 - p;
+        int n;
+        if (lv == 0) n = T.R >> T.J;
+        else n = T.nh[lv] * T.rows_h[lv] + (T.nsub_l[lv] - T.nh[lv]) * ((T.rows_v[lv] + 63) / 64);
+        it.item0[p + 1] = it.item0[p] + n;
+    }
+    for (int p = T.J + 2; p < kMaxLevels + 3; ++p) it.item0[p] = it.item0[T.J + 1];
+    return it;
+}
+
+}  // namespace
+
+hipError_t launch_mc(const MCArgs& a, hipStream_t st) {
+    const int64_t total = int64_t(a.batch) * a.T.ncoef;
+    if (total == 0) return hipSuccess;
+    mc_kernel<<<unsigned((total + NT - 1) / NT), NT, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rle(const RLEArgs& a, hipStream_t st) {
+    if (a.batch == 0) return hipSuccess;
+    const ItemTable it = items_of(a.T);
+    const int64_t waves = int64_t(it.item0[a.T.J + 1]) * a.batch;
+    const unsigned blocks = unsigned((waves + NT / 64 - 1) / (NT / 64));
+    rle_count_kernel<<<blocks, NT, 0, st>>>(a, it);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    rle_scan_kernel<<<a.batch, SCAN_NT, 0, st>>>(a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    rle_write_kernel<<<blocks, NT, 0, st>>>(a, it);
+    return hipGetLastError();
+}
+
+}  // namespace codec
+}  // namespace ct

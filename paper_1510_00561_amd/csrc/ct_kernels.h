@@ -82,7 +82,7 @@ struct SplitArgs {
     int64_t parent_plane, child_plane;  // plane strides of the two buffers
     float scale[64];    // per child channel (applied on store / load)
     int use_scale;
-    int bh;             // rows per streamed block (multiple of 4), see block_rows()
+    int bh;             // rows per streamed block (multiple of stream_row_align()), see block_rows()
     QuantIO q;          // final subbands as indices (analysis: written; synthesis: read)
 };
 
@@ -103,16 +103,18 @@ __host__ __device__ inline int block_rows(int rows, int col_items, int slots, in
     return bh;
 }
 
-// Work decomposition of the register-streaming split stages (one or two tree
-// levels per pass): every wavefront stores a strip of stream_cols() sheared
-// columns by SplitArgs::bh rows of one parent channel, and loads a halo of
-// stream_halo() rows and columns around it.
+// Work decomposition of the register-streaming split stages (one, two or
+// three tree levels per pass): every wavefront stores a strip of
+// stream_cols() sheared columns by SplitArgs::bh rows (a multiple of
+// stream_row_align()) of one parent channel, and loads halo rows above and
+// below and stream_halo_cols() columns on each side.
 __host__ __device__ constexpr int stream_cols_per_lane() { return 2; }
-__host__ __device__ constexpr int stream_halo(int levels) { return levels == 1 ? 4 : 12; }
+__host__ __device__ constexpr int stream_halo_cols(int levels) { return levels == 1 ? 4 : levels == 2 ? 6 : 14; }
 __host__ __device__ constexpr int stream_cols(int levels) {
-    return 64 * stream_cols_per_lane() - 2 * stream_halo(levels);
+    return 64 * stream_cols_per_lane() - 2 * stream_halo_cols(levels);
 }
-__host__ __device__ constexpr int stream_max_rows(int levels) { return levels == 1 ? 248 : 216; }
+__host__ __device__ constexpr int stream_max_rows(int levels) { return levels == 2 ? 216 : 248; }
+__host__ __device__ constexpr int stream_row_align(int levels) { return levels == 3 ? 8 : 4; }
 
 // Per plane: horizontal parents first (each with `ih` items, `sh` strips
 // across), then vertical ones (`iv`, `sv`).
@@ -152,6 +154,9 @@ hipError_t launch_dfb_split_synthesis(const SplitArgs& a, Lift lift, int batch, 
 // at level t+1 (stored back to back in subband order), and back.
 hipError_t launch_dfb_split2_analysis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
 hipError_t launch_dfb_split2_synthesis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
+// Tree levels t, t+1 and t+2 in one pass.
+hipError_t launch_dfb_split3_analysis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
+hipError_t launch_dfb_split3_synthesis(const SplitArgs& a, Lift lift, int batch, hipStream_t s);
 
 // Folds the mirrored padding back onto its sources (transpose of padding):
 // out[r][c] = sum of in[r'][c'] over r' in {r, 2H-1-r}, c' in {c, 2W-1-c}

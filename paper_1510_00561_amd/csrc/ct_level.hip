@@ -1,5 +1,5 @@
 // Per-stage kernels for gfx950: the fused LP level + DFB tree levels 1-2
-// (analysis and synthesis), the deeper DFB tree levels one or two at a time,
+// (analysis and synthesis), the deeper DFB tree levels one, two or three at a time,
 // all register-streaming, and the transpose of the mirror padding.
 //
 // Paper section 2.1 (LP, then a DFB on each bandpass image, 9-7 filters),
@@ -32,11 +32,12 @@ __global__ __launch_bounds__(NT_STREAM) void stream_level_synthesis_kernel(stage
     st.template run_tile<Q>(xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
-// One wavefront per (plane, parent channel, column strip, row block).
-template <int LEVELS, bool ANA, bool Q>
+// One wavefront per (plane, parent channel, column strip, row block); FO is
+// the lifting's first_odd.
+template <int LEVELS, bool ANA, bool Q, int FO>
 __global__ __launch_bounds__(NT_STREAM) void stream_split_kernel(SplitArgs a, Lift L, int batch) {
     stream::StreamSplit<LEVELS, ANA, NT_STREAM> st(a, batch, L);
-    st.template run_tile<Q>(xcd_remap(blockIdx.x, gridDim.x));
+    st.template run_tile<Q, FO>(xcd_remap(blockIdx.x, gridDim.x));
 }
 
 __global__ __launch_bounds__(256) void pad_fold_kernel(CView in, int R, int C, View out, int H,
@@ -84,12 +85,14 @@ hipError_t launch_level_synthesis(const stage::LevelSynArgs& a, int lo_r, hipStr
 
 template <int LEVELS, bool ANA>
 static hipError_t launch_split(const SplitArgs& a, Lift lift, int batch, hipStream_t st) {
-    if (a.bh <= 0 || (a.bh & 3)) return hipErrorInvalidValue;
+    if (a.bh <= 0 || a.bh % stream_row_align(LEVELS)) return hipErrorInvalidValue;
     if ((a.Rj & 3) || (a.Cj & 3)) return hipErrorInvalidValue;   // channel rows of even width
     constexpr int waves = NT_STREAM / 64;
     const int tiles = (stream_items(a, batch, LEVELS) + waves - 1) / waves;
-    if (a.q.idx) stream_split_kernel<LEVELS, ANA, true><<<tiles, NT_STREAM, 0, st>>>(a, lift, batch);
-    else stream_split_kernel<LEVELS, ANA, false><<<tiles, NT_STREAM, 0, st>>>(a, lift, batch);
+    if (a.q.idx && lift.first_odd) stream_split_kernel<LEVELS, ANA, true, 1><<<tiles, NT_STREAM, 0, st>>>(a, lift, batch);
+    else if (a.q.idx) stream_split_kernel<LEVELS, ANA, true, 0><<<tiles, NT_STREAM, 0, st>>>(a, lift, batch);
+    else if (lift.first_odd) stream_split_kernel<LEVELS, ANA, false, 1><<<tiles, NT_STREAM, 0, st>>>(a, lift, batch);
+    else stream_split_kernel<LEVELS, ANA, false, 0><<<tiles, NT_STREAM, 0, st>>>(a, lift, batch);
     return hipGetLastError();
 }
 
@@ -104,6 +107,12 @@ hipError_t launch_dfb_split2_analysis(const SplitArgs& a, Lift lift, int batch, 
 }
 hipError_t launch_dfb_split2_synthesis(const SplitArgs& a, Lift lift, int batch, hipStream_t st) {
     return launch_split<2, false>(a, lift, batch, st);
+}
+hipError_t launch_dfb_split3_analysis(const SplitArgs& a, Lift lift, int batch, hipStream_t st) {
+    return launch_split<3, true>(a, lift, batch, st);
+}
+hipError_t launch_dfb_split3_synthesis(const SplitArgs& a, Lift lift, int batch, hipStream_t st) {
+    return launch_split<3, false>(a, lift, batch, st);
 }
 
 hipError_t launch_pad_fold(CView in, int R, int C, View out, int H, int W, int batch,

@@ -8,9 +8,10 @@
 // position over all streams; its launch covers all their tiles.
 //
 // Autotuning (CT_PLAN_AUTOTUNE) picks, for every distinct LP level shape
-// with four or more DFB tree levels, whether the deeper tree levels run in
-// pairs (one streaming pass per two levels, halo 12) or one at a time (one
-// pass per level, halo 4), by timing both with HIP events. Choices are cached in a JSON file keyed by device
+// with four or more DFB tree levels, how many of the deeper tree levels run
+// per streaming pass (one, two or three: halo 4, 12 or 28 rows), by timing
+// every grouping with HIP events. All groupings compute the same float32
+// operations in the same order, so the choice never changes a result. Choices are cached in a JSON file keyed by device
 // architecture and shape (CT_AUTOTUNE_CACHE, default
 // $HOME/.cache/ct_autotune.json).
 #include <stdio.h>
@@ -47,7 +48,7 @@ struct ct_plan {
     int* d_first = nullptr;
     int nstages = 0;
     int total_items = 0;
-    double bytes = 0;
+    double bytes = 0, alg = 0;
     hipStream_t capture = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -113,12 +114,16 @@ float time_level_splits(int Rj, int Cj, int l, int batch, int grouping, float* A
                         float* D, int64_t plane, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     int first[4], count[4], ng = 0;
     for (int t = 3; t <= l;) {
-        const int c = (grouping == 2 && t + 1 <= l) ? 2 : 1;
+        const int c = t + grouping - 1 <= l ? grouping : l - t + 1;
         first[ng] = t;
         count[ng] = c;
         ++ng;
         t += c;
     }
+    static hipError_t (*const ana[3])(const SplitArgs&, Lift, int, hipStream_t) = {
+        launch_dfb_split_analysis, launch_dfb_split2_analysis, launch_dfb_split3_analysis};
+    static hipError_t (*const syn[3])(const SplitArgs&, Lift, int, hipStream_t) = {
+        launch_dfb_split_synthesis, launch_dfb_split2_synthesis, launch_dfb_split3_synthesis};
     Lift L{{-1.5f, -0.05f, 0.88f, 0.44f}, 1};
     auto run = [&]() -> bool {
         float* cur = A;
@@ -135,8 +140,7 @@ float time_level_splits(int Rj, int Cj, int l, int batch, int grouping, float* A
             a.child_plane = plane;
             a.plane_elems = int64_t(Rj) * Cj;
             a.bh = split_block_rows(a, batch, count[gi]);
-            hipError_t e = count[gi] == 2 ? launch_dfb_split2_analysis(a, L, batch, st)
-                                          : launch_dfb_split_analysis(a, L, batch, st);
+            hipError_t e = ana[count[gi] - 1](a, L, batch, st);
             if (e != hipSuccess) return false;
             std::swap(cur, other);
         }
@@ -154,8 +158,7 @@ float time_level_splits(int Rj, int Cj, int l, int batch, int grouping, float* A
             a.child_plane = plane;
             a.plane_elems = int64_t(Rj) * Cj;
             a.bh = split_block_rows(a, batch, count[gi]);
-            hipError_t e = count[gi] == 2 ? launch_dfb_split2_synthesis(a, L, batch, st)
-                                          : launch_dfb_split_synthesis(a, L, batch, st);
+            hipError_t e = syn[count[gi] - 1](a, L, batch, st);
             if (e != hipSuccess) return false;
             std::swap(cur2, other2);
         }
@@ -203,13 +206,22 @@ int autotune(ct_plan* p, hipStream_t st) {
                 float* B = reinterpret_cast<float*>(ws + w.b_off);
                 float* D = reinterpret_cast<float*>(ws + w.d_off);
                 const int64_t plane = int64_t(g.R) * g.C;
-                const float t2 = time_level_splits(Rj, Cj, l, batch, 2, A, B, D, plane, st, e0, e1);
-                const float t1 = time_level_splits(Rj, Cj, l, batch, 1, A, B, D, plane, st, e0, e1);
-                if (t1 < 0 || t2 < 0) {
-                    rc = CT_ERR_HIP;
-                    break;
+                // every grouping that differs for this depth: up to l - 2
+                // levels per pass
+                float best = -1.f;
+                choice = 1;
+                for (int grp = 1; grp <= 3 && grp <= l - 2; ++grp) {
+                    const float ms = time_level_splits(Rj, Cj, l, batch, grp, A, B, D, plane, st, e0, e1);
+                    if (ms < 0) {
+                        rc = CT_ERR_HIP;
+                        break;
+                    }
+                    if (best < 0 || ms < best) {
+                        best = ms;
+                        choice = grp;
+                    }
                 }
-                choice = t1 < t2 ? 1 : 2;
+                if (rc != CT_OK) break;
                 cache[key] = choice;
                 dirty = true;
             }
@@ -268,7 +280,7 @@ int ct_plan_create(const ct_stream_desc* streams, int32_t n, int32_t flags, ct_p
     p->geoms.resize(n);
     p->wls.resize(n);
     p->ws_off.resize(n);
-    p->grouping.assign(size_t(n) * kMaxLevels, 2);
+    p->grouping.assign(size_t(n) * kMaxLevels, 3);
     size_t total = 0;
     for (int s = 0; s < n; ++s) {
         const int rc = check_stream(streams[s], &p->geoms[s], (flags & CT_PLAN_FUSED) != 0);
@@ -351,6 +363,7 @@ int ct_plan_create(const ct_stream_desc* streams, int32_t n, int32_t flags, ct_p
                 first.push_back(g.tiles);
                 g.tiles += d.ntiles;
                 p->bytes += d.bytes;
+                p->alg += d.alg;
                 order.push_back(d);
             }
             items += g.tiles;
@@ -389,10 +402,10 @@ int ct_plan_create(const ct_stream_desc* streams, int32_t n, int32_t flags, ct_p
 int ct_plan_run(ct_plan* p, hipStream_t stream) {
     if (!p) return CT_ERR_ARG;
     if (p->exec) {
-        CT_PROFILED("batched_graph", p->bytes, hipGraphLaunch(p->exec, stream), stream);
+        CT_PROFILED_ALG("batched_graph", p->bytes, p->alg, hipGraphLaunch(p->exec, stream), stream);
         return CT_OK;
     }
-    CT_PROFILED("batched", p->bytes, launch_groups(p, stream), stream);
+    CT_PROFILED_ALG("batched", p->bytes, p->alg, launch_groups(p, stream), stream);
     return CT_OK;
 }
 
@@ -413,12 +426,17 @@ int ct_plan_info(const ct_plan* p, ct_plan_info_t* info) {
     info->launches = int32_t(p->groups.size());
     info->graph = p->exec ? 1 : 0;
     info->autotuned = p->autotuned;
-    int pairs = 0, singles = 0;
+    int n[4] = {0, 0, 0, 0};
     for (size_t s = 0; s < p->streams.size(); ++s)
-        for (int j = 0; j < p->geoms[s].J; ++j)
-            if (p->geoms[s].l[j] >= 4) (p->grouping[s * kMaxLevels + j] == 2 ? pairs : singles)++;
-    info->levels_paired = pairs;
-    info->levels_single = singles;
+        for (int j = 0; j < p->geoms[s].J; ++j) {
+            const int l = p->geoms[s].l[j];
+            int grp = p->grouping[s * kMaxLevels + j];
+            if (grp > l - 2) grp = l - 2;       // the same passes as l - 2 levels per pass
+            if (l >= 4) n[grp]++;
+        }
+    info->levels_single = n[1];
+    info->levels_paired = n[2];
+    info->levels_triple = n[3];
     info->workspace_bytes = 0;
     for (size_t s = 0; s < p->streams.size(); ++s) info->workspace_bytes += p->wls[s].total;
     return CT_OK;

@@ -13,19 +13,22 @@ namespace ct {
 // on `st` when constructed and another at done(), only while profiling is on.
 struct ProfScope {
     const char* name;
-    double bytes;
+    double bytes, alg;
     hipStream_t st;
     hipEvent_t a = nullptr, b = nullptr;
-    ProfScope(const char* n, double by, hipStream_t s);
+    ProfScope(const char* n, double by, double al, hipStream_t s);
     void done();
 };
 
-#define CT_PROFILED(name, bytes, expr, stream)                       \
-    do {                                                             \
-        ::ct::ProfScope ct_prof_scope_(name, double(bytes), stream); \
-        if ((expr) != hipSuccess) return CT_ERR_HIP;                 \
-        ct_prof_scope_.done();                                       \
+// `bytes`: compulsory bytes of the launch; `alg`: the algorithmic part of
+// them (CT_PROFILED: all of them).
+#define CT_PROFILED_ALG(name, bytes, alg, expr, stream)                            \
+    do {                                                                           \
+        ::ct::ProfScope ct_prof_scope_(name, double(bytes), double(alg), stream); \
+        if ((expr) != hipSuccess) return CT_ERR_HIP;                               \
+        ct_prof_scope_.done();                                                     \
     } while (0)
+#define CT_PROFILED(name, bytes, expr, stream) CT_PROFILED_ALG(name, bytes, bytes, expr, stream)
 
 // Transform modes, in the order used by build_transform_chain.
 enum ChainMode { kModeForward = 0, kModeInverse = 1, kModeForwardAdjoint = 2, kModeInverseAdjoint = 3 };
@@ -67,7 +70,7 @@ inline int level_stage_tiles(int R, int C, int batch, int bh) {
     return (level_items(R, C, batch, bh) + waves - 1) / waves;
 }
 
-// Work-queue tiles of a DFB split stage covering `levels` (1 or 2) tree
+// Work-queue tiles of a DFB split stage covering `levels` (1, 2 or 3) tree
 // levels: one wavefront item per strip, kBatchedThreads / 64 per tile.
 inline int split_stage_tiles(const SplitArgs& a, int batch, int levels) {
     constexpr int waves = kBatchedThreads / 64;

@@ -73,15 +73,6 @@ __device__ __forceinline__ SplitGeom split_geom(const SplitArgs& A, int pp) {
     return g;
 }
 
-// Channel position of grandchild class (row i & 3) of parent pp at level t+1.
-__device__ __forceinline__ int grandchild_pos(bool vertical, int pp, int cls) {
-    // horizontal: even child 2pp+1 (children 4pp+3, 4pp+2), odd child 2pp (4pp+1, 4pp)
-    // vertical:   even child 2pp   (children 4pp, 4pp+1),   odd child 2pp+1 (4pp+2, 4pp+3)
-    const int h = (cls & 1) ? 1 - (cls >> 1) : 3 - (cls >> 1);
-    const int v = ((cls & 1) << 1) | (cls >> 1);
-    return 4 * pp + (vertical ? v : h);
-}
-
 }  // namespace stage
 
 // Per-stage launches of the LP-level stages (`lo_r` = reach of the lowpass

@@ -7,7 +7,8 @@ missing or a call fails, an exception is raised.
 
 Names follow the C ABI (include/ct.h): forward, inverse, quantize,
 dequantize, forward_adjoint, inverse_adjoint, layout, rgb_to_ycocg,
-ycocg_to_rgb, lowpass_diff, motion_search.
+ycocg_to_rgb, lowpass_diff, motion_search, mc_residual, rle_encode,
+rle_decode_host, deflate_host, inflate_host.
 """
 import ctypes
 import os
@@ -44,7 +45,8 @@ class Subband(ctypes.Structure):
 
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
-                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double)]
 
 
 class StreamDesc(ctypes.Structure):
@@ -60,7 +62,7 @@ class PlanInfo(ctypes.Structure):
                 ("work_items", ctypes.c_int32), ("launches", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("autotuned", ctypes.c_int32),
                 ("levels_paired", ctypes.c_int32), ("levels_single", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("levels_triple", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
 
 
 PLAN_GRAPH = 1
@@ -103,6 +105,12 @@ def _lib():
             "ct_ycocg_to_rgb": [i32, i32, i32, i32, P, P, P, P, P],
             "ct_lowpass_diff": [G, i32, P, i32, P],
             "ct_motion_search": [i32, i32, i32, i32, P, P, P, P, P],
+            "ct_mc_residual": [G, i32, i32, P, P, P, i32, i32, i32, i32, P, P],
+            "ct_rle_workspace_bytes": [G, i32, ctypes.POINTER(sz)],
+            "ct_rle_encode": [G, i32, P, i32, P, P, P, sz, P],
+            "ct_rle_decode_host": [G, P, P, i32, P],
+            "ct_deflate_host": [P, P, i32, i32, i32, P, sz, P, ctypes.POINTER(sz)],
+            "ct_inflate_host": [P, P, P, i32, i32, P],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -152,14 +160,19 @@ def profile_enable(on=True, max_launches=0):
     _check("ct_profile_enable", _lib().ct_profile_enable(1 if on else 0, int(max_launches)))
 
 
-def profile_collect():
-    """{kernel: (launches, total_ms, bytes)} since the last collect."""
+def profile_collect(alg=False):
+    """{kernel: (launches, total_ms, compulsory bytes)} since the last collect;
+    with alg=True the tuples also carry the algorithmic bytes."""
     cap = 64
     out = (KernelStat * cap)()
     n = ctypes.c_int32(0)
     _check("ct_profile_collect", _lib().ct_profile_collect(out, cap, ctypes.byref(n)))
-    return {out[i].name.decode(): (int(out[i].launches), float(out[i].total_ms), float(out[i].bytes))
-            for i in range(min(n.value, cap))}
+    res = {}
+    for i in range(min(n.value, cap)):
+        s = out[i]
+        t = (int(s.launches), float(s.total_ms), float(s.bytes))
+        res[s.name.decode()] = t + (float(s.alg_bytes),) if alg else t
+    return res
 
 
 def workspace_bytes(height, width, levels, dirs, batch):
@@ -292,6 +305,59 @@ class Plan:
         _check("ct_lowpass_diff", rc)
         return idx
 
+    def mc_residual(self, cur, prev, mv, n=1, group=1, inverse=False, out=None):
+        """P-frame components (ct_mc_residual): cur - prediction(prev), or with
+        inverse=True cur + prediction(prev); int16 [B, ncoef]. mv is the int16
+        [ceil(B / group), nby, nbx, 2] output of motion_search."""
+        B = self.batch
+        self._check_tensor(cur, (B, self.ncoef), torch.int16, "cur")
+        self._check_tensor(prev, (B, self.ncoef), torch.int16, "prev")
+        if mv.dim() != 4 or mv.shape[0] != -(-B // group) or mv.shape[3] != 2:
+            raise ValueError("mv must be [ceil(B / group), nby, nbx, 2]")
+        self._check_tensor(mv, tuple(mv.shape), torch.int16, "mv")
+        if out is None:
+            out = torch.empty_like(cur)
+        self._check_tensor(out, (B, self.ncoef), torch.int16, "out")
+        rc = _lib().ct_mc_residual(ctypes.byref(self.g), B, int(n), ctypes.c_void_p(cur.data_ptr()),
+                                   ctypes.c_void_p(prev.data_ptr()), ctypes.c_void_p(mv.data_ptr()),
+                                   int(mv.shape[1]), int(mv.shape[2]), int(group), 1 if inverse else 0,
+                                   ctypes.c_void_p(out.data_ptr()), self._stream())
+        _check("ct_mc_residual", rc)
+        return out
+
+    def rle_encode(self, idx, p_frame, symbols=None, sub_off=None):
+        """Zero-run coding (ct_rle_encode): (symbols int16 [B, 2 ncoef], sub_off
+        int32 [B, nsub + 1]); plane b's stream is symbols[b, :sub_off[b, -1]]."""
+        B = self.batch
+        self._check_tensor(idx, (B, self.ncoef), torch.int16, "idx")
+        if symbols is None:
+            symbols = torch.empty((B, 2 * self.ncoef), dtype=torch.int16, device=idx.device)
+        if sub_off is None:
+            sub_off = torch.empty((B, self.nsub + 1), dtype=torch.int32, device=idx.device)
+        self._check_tensor(symbols, (B, 2 * self.ncoef), torch.int16, "symbols")
+        self._check_tensor(sub_off, (B, self.nsub + 1), torch.int32, "sub_off")
+        if not hasattr(self, "_rle_ws"):
+            n = ctypes.c_size_t(0)
+            _check("ct_rle_workspace_bytes", _lib().ct_rle_workspace_bytes(ctypes.byref(self.g), B, ctypes.byref(n)))
+            self._rle_ws = torch.empty(max(1, n.value), dtype=torch.uint8, device=self.device)
+        rc = _lib().ct_rle_encode(ctypes.byref(self.g), B, ctypes.c_void_p(idx.data_ptr()), 1 if p_frame else 0,
+                                  ctypes.c_void_p(symbols.data_ptr()), ctypes.c_void_p(sub_off.data_ptr()),
+                                  ctypes.c_void_p(self._rle_ws.data_ptr()), self._rle_ws.numel(), self._stream())
+        _check("ct_rle_encode", rc)
+        return symbols, sub_off
+
+    def rle_decode_host(self, symbols, sub_off, p_frame):
+        """One plane's indices from its symbol stream (ct_rle_decode_host, host
+        code): symbols int16 and sub_off int32 numpy arrays."""
+        import numpy as np
+        sym = np.ascontiguousarray(symbols, dtype=np.int16)
+        off = np.ascontiguousarray(sub_off, dtype=np.int32)
+        out = np.empty(self.ncoef, dtype=np.int16)
+        rc = _lib().ct_rle_decode_host(ctypes.byref(self.g), sym.ctypes.data, off.ctypes.data,
+                                       1 if p_frame else 0, out.ctypes.data)
+        _check("ct_rle_decode_host", rc)
+        return out
+
     def encode(self, x, steps, idx=None, side=None, coeffs=None):
         """Fused forward CT + quantise: (idx [B, ncoef] int16, side [B, 2]);
         `coeffs` (optional [B, ncoef] float32) also receives the coefficients."""
@@ -400,6 +466,36 @@ def ycocg_to_rgb(y, co, cg, n, out=None):
                                 ctypes.c_void_p(out.data_ptr()), st)
     _check("ct_ycocg_to_rgb", rc)
     return out
+
+
+def deflate_host(symbols, sub_off, mode=0, level=6):
+    """DEFLATE of one plane's symbol stream (ct_deflate_host): (compressed
+    bytes, per-part byte counts); mode 0 per component, mode 1 whole plane."""
+    import numpy as np
+    sym = np.ascontiguousarray(symbols, dtype=np.int16)
+    off = np.ascontiguousarray(sub_off, dtype=np.int32)
+    nsub = len(off) - 1
+    cap = 2 * sym.nbytes + 64 * nsub + 1024
+    out = np.empty(cap, dtype=np.uint8)
+    parts = np.zeros(nsub if mode == 0 else 1, dtype=np.uint32)
+    total = ctypes.c_size_t(0)
+    rc = _lib().ct_deflate_host(sym.ctypes.data, off.ctypes.data, nsub, int(mode), int(level), out.ctypes.data,
+                                cap, parts.ctypes.data, ctypes.byref(total))
+    _check("ct_deflate_host", rc)
+    return out[:total.value].tobytes(), parts
+
+
+def inflate_host(blob, parts, sub_off, mode=0):
+    """Inverse of deflate_host: the int16 symbol stream."""
+    import numpy as np
+    off = np.ascontiguousarray(sub_off, dtype=np.int32)
+    buf = np.frombuffer(blob, dtype=np.uint8).copy()
+    parts = np.ascontiguousarray(parts, dtype=np.uint32)
+    sym = np.empty(int(off[-1]), dtype=np.int16)
+    rc = _lib().ct_inflate_host(buf.ctypes.data, parts.ctypes.data, off.ctypes.data, len(off) - 1, int(mode),
+                                sym.ctypes.data)
+    _check("ct_inflate_host", rc)
+    return sym
 
 
 def motion_search(cur, prev, w, mv=None, ssd=None, want_ssd=True):

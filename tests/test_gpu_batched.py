@@ -30,6 +30,7 @@ STREAMS = [
     (256, 256, 2, [8, 4], 1),
     (40, 40, 3, [8, 4, 4], 3),      # odd coefficient count
     (4, 4, 1, [8], 2),              # smallest frame
+    (128, 128, 1, [64], 1),         # six tree levels: three per pass, then one
 ]
 
 
@@ -147,7 +148,7 @@ def test_autotuned_plan(tmp_path, monkeypatch):
     assert info["levels_paired"] + info["levels_single"] > 0
     assert cache.exists()
     entries = json.loads(cache.read_text())
-    assert entries and all(v in (1, 2) for v in entries.values())
+    assert entries and all(v in (1, 2, 3) for v in entries.values())
     assert set(_grouping_keys(STREAMS)) <= set(entries)
     plan.run()
     torch.cuda.synchronize()
@@ -168,19 +169,24 @@ def test_split_groupings_are_bit_identical(tmp_path, monkeypatch):
     keys = _grouping_keys(STREAMS)
     assert keys
     snaps = []
-    for choice in (1, 2):
+    for choice in (1, 2, 3):
         cache = tmp_path / f"forced{choice}.json"
         cache.write_text(json.dumps({k: choice for k in keys}))
         monkeypatch.setenv("CT_AUTOTUNE_CACHE", str(cache))
         plan = ct.Batched(_streams(5), graph=True, autotune=True)
         info = plan.info()
-        assert (info["levels_single"] if choice == 1 else info["levels_paired"]) == len(keys)
+        assert info["levels_single"] + info["levels_paired"] + info["levels_triple"] == len(keys)
+        if choice == 1:
+            assert info["levels_single"] == len(keys)
+        else:
+            assert info["levels_single"] == 0
         plan.run()
         torch.cuda.synchronize()
         snaps.append(_snapshot(plan))
         plan.close()
         print(f"[batched] grouping {choice} done", flush=True)
     _same(snaps[0], snaps[1])
+    _same(snaps[0], snaps[2])
 
 
 def test_fused_plan_equals_encode_decode():
