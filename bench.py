@@ -9,9 +9,10 @@ from 4..64. Inputs are resident in HBM before timing starts.
 Prints one JSON line. `value` is frames/s (real 1080p frames). The line also
 carries the effective HBM bandwidth of the step (algorithmic bytes / time),
 the roofline of the dominant kernel from live per-launch HIP events, the
-colour front end / back end and K-frame lowpass filter measured on the same
-frames (outside the step), and the FP64 oracle timed on the host cores on a
-bounded sample.
+colour front end / back end, the K-frame lowpass filter, the motion search and
+the codec back end (P-frame components, zero-run coding, DEFLATE) measured on
+the same frames (outside the step), a copy kernel as the attainable ceiling,
+and the FP64 oracle timed on the host cores on a bounded sample.
 """
 import argparse
 import hashlib
@@ -38,6 +39,8 @@ KERNEL_SOURCES = {   # the kernel's code and the host code that sets its launch 
     "dfb_split_synthesis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h", "ct_api.cpp"),
     "dfb_split2_analysis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h", "ct_api.cpp"),
     "dfb_split2_synthesis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h", "ct_api.cpp"),
+    "dfb_split3_analysis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h", "ct_api.cpp"),
+    "dfb_split3_synthesis": ("ct_level.hip", "ct_stream.h", "ct_stages.h", "ct_kernels.h", "ct_api.cpp"),
     "pad_fold": ("ct_level.hip",),
     "lowpass_partial": ("ct_quant.hip", "ct_quant_stages.h"),
     "quantize": ("ct_quant.hip", "ct_quant_stages.h"),
@@ -47,6 +50,8 @@ KERNEL_SOURCES = {   # the kernel's code and the host code that sets its launch 
     "lowpass_diff": ("ct_color.hip", "ct_color_stages.h", "ct_color_api.cpp"),
     "lowpass_undiff": ("ct_color.hip", "ct_color_stages.h", "ct_color_api.cpp"),
     "motion_search": ("ct_motion.hip", "ct_motion.h", "ct_motion_api.cpp"),
+    "mc_residual": ("ct_codec.hip", "ct_codec.h", "ct_codec_api.cpp"),
+    "rle_encode": ("ct_codec.hip", "ct_codec.h", "ct_codec_api.cpp"),
 }
 
 
@@ -63,7 +68,7 @@ def source_digest(name):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name, bytes_per_launch, summary="traffic_1080p.json"):
+def measured_traffic(name, bytes_per_launch=None, summary="traffic_1080p.json"):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if current."""
     path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
@@ -76,31 +81,59 @@ def measured_traffic(name, bytes_per_launch, summary="traffic_1080p.json"):
     return ent.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(rgb_frame, steps_np, seconds_budget=30.0):
-    """The FP64 oracle on one 1080p YCoCg frame (3 planes), single process."""
+def _oracle_plane(args):
+    """One plane through the FP64 oracle: forward, quantise, dequantise, inverse."""
     import numpy as np
-    from oracle import color
     from oracle import ct as oct
     from oracle import geometry as geo
     from oracle import quant as oq
+    x, steps = args
     table = geo.subband_table(H, W, J, DIRS)
-    planes_np = np.stack(color.encode_frame(rgb_frame, 1))
+    c = oct.forward(np.asarray(x, np.float64), J, DIRS)
+    q, side = oq.quantize64(c, np.asarray(steps, np.float64), table)
+    d = oq.dequantize64(q, np.asarray(steps, np.float64), side, table)
+    oct.inverse(d, H, W, J, DIRS)
+    return 1
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(rgb_frames, steps_np, workers=None):
+    """The FP64 oracle on the host cores: one plane in one process (latency),
+    then a process pool over up to three planes per worker (throughput)."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import color
+    planes = [p for fr in rgb_frames for p in color.encode_frame(fr, 1)]
+    jobs = [(planes[i], steps_np[i % 3]) for i in range(len(planes))]
     t0 = time.perf_counter()
-    n = 0
-    for b in range(3):
-        x = planes_np[b].astype(np.float64)
-        c = oct.forward(x, J, DIRS)
-        q, side = oq.quantize64(c, steps_np[b % 3].astype(np.float64), table)
-        d = oq.dequantize64(q, steps_np[b % 3].astype(np.float64), side, table)
-        oct.inverse(d, H, W, J, DIRS)
-        n += 1
-        if time.perf_counter() - t0 > seconds_budget:
-            break
-    dt = time.perf_counter() - t0
-    frames = n / 3.0
-    return {"value": frames / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} of the 3 planes of one 1080p YCoCg frame, forward+quantise+dequantise+inverse "
-                      f"in FP64 NumPy, one process ({dt:.1f} s)"}
+    _oracle_plane(jobs[0])
+    latency = time.perf_counter() - t0
+    # a GPU box gives this process a share of 16 cores, whatever the host count
+    workers = workers or max(1, min(16, os.cpu_count() or 1))
+    n = min(len(jobs), 3 * workers)
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_plane, jobs[:workers])          # start-up and first-touch, untimed
+        t0 = time.perf_counter()
+        pool.map(_oracle_plane, jobs[:n])
+        dt = time.perf_counter() - t0
+    return {"value": round(n / 3.0 / dt, 4), "unit": "frames/s", "cores": workers, "kind": "oracle",
+            "cpu": cpu_model(), "numpy_threads": os.environ.get("OMP_NUM_THREADS", "default"),
+            "single_plane_latency_s": round(latency, 2),
+            "single_process_frames_per_s": round(1.0 / 3.0 / latency, 4),
+            "sample": f"{n} planes (Y, Co, Cg of {n // 3} 1080p frames) forward+quantise+dequantise+inverse "
+                      f"in FP64 NumPy over a pool of {workers} processes ({dt:.1f} s); latency of one "
+                      f"plane in one process {latency:.1f} s"}
 
 
 def ycocg_planes(rgb):
@@ -197,6 +230,28 @@ def motion_stage(planes, steps, w=8):
             "moving_blocks": int((mv != 0).any(dim=-1).sum())}
 
 
+def copy_ceiling(steps):
+    """Attainable bandwidth: a plain streaming copy (read + write, 1 GiB each way)
+    timed with HIP events on the current stream."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    gbps = 8.0 * n / (ms * 1e-3) / 1e9
+    del a, b
+    return {"kernel": "torch.mul(a, 1.0, out=b) over 2^28 floats", "bytes_per_launch": 8 * n,
+            "avg_launch_us": round(ms * 1e3, 2), "gbps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4)}
+
+
 def batched_comparison(steps):
     """Mixed workload: 64 streams (one YCoCg frame each) of 320x240, 640x480 or
     1280x720, LP depth 2-4, 8-16 directions, as one graph launch of grouped
@@ -238,13 +293,81 @@ def batched_comparison(steps):
 
     t_plain = timed(plan.run_plain)
     t_graph = timed(plan.run)
+    ct.profile_enable(True, 64)
+    plan.run()
+    torch.cuda.synchronize()
+    stats = ct.profile_collect(alg=True)
+    ct.profile_enable(False)
+    _, _, comp_b, alg_b = stats["batched_graph"]
     info = plan.info()
     plan.close()
     return {"workload": "64 streams (one YCoCg frame each) drawn from 320x240/640x480/1280x720, "
                         "LP depth 2-4, 8-16 directions, fused encoder + decoder",
             "t_plain_ms": round(t_plain, 3), "t_batched_graph_ms": round(t_graph, 3),
             "speedup": round(t_plain / t_graph, 3), "frames_per_s_batched": round(64 / (t_graph / 1e3), 1),
+            "alg_bytes_per_run": alg_b, "compulsory_bytes_per_run": comp_b,
+            "hbm_alg_gbps": round(alg_b / (t_graph * 1e-3) / 1e9, 1),
+            "hbm_alg_frac": round(alg_b / (t_graph * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "hbm_compulsory_frac": round(comp_b / (t_graph * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
             "bit_identical_to_plain": identical, "plan": info}
+
+
+def codec_back_end(plan, x, steps, reps):
+    """The codec stages after the quantiser on the step's 16 frames: frame 0 is a
+    K-frame, frames 1..15 P-frames (vectors from the motion search on the Y
+    planes, w = 8). Device times of the P-frame components and the zero-run
+    coder; DEFLATE (host) on the first K-frame and the first P-frame gives the
+    coded size."""
+    import numpy as np
+    import torch
+    from paper_1510_00561_amd import ct
+    idx, side = plan.encode(x, steps)
+    B = x.shape[0]
+    y = x[0::3]
+    mv, _ = ct.motion_search(y[1:].contiguous(), y[:-1].contiguous(), 8)
+    pl = ct.Plan(H, W, J, DIRS, B - 3, "cuda:0")
+    cur, prev = idx[3:].contiguous(), idx[:-3].contiguous()
+    res = pl.mc_residual(cur, prev, mv, n=1, group=3)
+    pk = ct.Plan(H, W, J, DIRS, 3, "cuda:0")
+    k_sym, k_off = pk.rle_encode(idx[:3].contiguous(), 0)
+    p_sym, p_off = pl.rle_encode(res, 1)
+    back = pl.mc_residual(res, prev, mv, n=1, group=3, inverse=True)
+    torch.cuda.synchronize()
+    restored = bool(torch.equal(back, cur))
+    ct.profile_enable(True, 1024)
+    for _ in range(reps):
+        pl.mc_residual(cur, prev, mv, n=1, group=3, out=res)
+        pl.rle_encode(res, 1, p_sym, p_off)
+    torch.cuda.synchronize()
+    stats = ct.profile_collect(alg=True)
+    ct.profile_enable(False)
+    dev = {}
+    for name, (n, tms, by, al) in stats.items():
+        us = tms / n * 1e3
+        dev[name] = {"avg_launch_us": round(us, 2), "bytes_per_launch": by / n,
+                     "gbps": round(by / n / (us * 1e3), 1), "frac": round(by / n / (us * 1e3) / HBM_PEAK_GBPS, 4)}
+    k_sym_h, k_off_h = k_sym.cpu().numpy(), k_off.cpu().numpy()
+    p_sym_h, p_off_h = p_sym.cpu().numpy(), p_off.cpu().numpy()
+    sizes = {}
+    t0 = time.perf_counter()
+    for kind, symh, offh, planes in (("k_frame", k_sym_h, k_off_h, range(3)), ("p_frame", p_sym_h, p_off_h, range(3))):
+        tot_scal, tot_nts, syms = 0, 0, 0
+        for b in planes:
+            s_b = symh[b, :offh[b, -1]]
+            blob, _ = ct.deflate_host(s_b, offh[b], 0)
+            blob1, _ = ct.deflate_host(s_b, offh[b], 1)
+            tot_scal += len(blob)
+            tot_nts += len(blob1)
+            syms += int(offh[b, -1])
+        sizes[kind] = {"symbols": syms, "bytes_scalable": tot_scal, "bytes_nts": tot_nts,
+                       "bits_per_pixel_scalable": round(8.0 * tot_scal / (H * W), 4),
+                       "bits_per_pixel_nts": round(8.0 * tot_nts / (H * W), 4)}
+    deflate_s = time.perf_counter() - t0
+    del pl, pk
+    return {"workload": f"{B // 3} YCoCg 1080p frames: frame 0 a K-frame, frames 1..{B // 3 - 1} P-frames "
+                        f"(motion search w=8 on Y, vectors shared by the three channels)",
+            "kernels": dev, "p_frames_restored_exactly": restored,
+            "deflate_host_s_for_two_frames": round(deflate_s, 3), "sizes_first_frames": sizes}
 
 
 def main():
@@ -257,10 +380,13 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-separate", action="store_true",
                     help="skip timing the four separate calls (profiling runs)")
-    ap.add_argument("--mode", choices=["bench", "copy", "colour", "motion"], default="bench",
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the step only: no colour, motion or codec stages (counter runs)")
+    ap.add_argument("--mode", choices=["bench", "copy", "colour", "motion", "codec"], default="bench",
                     help="copy: stream 1 GiB through a plain elementwise kernel (counter calibration); "
                          "colour: only the colour and K-frame stages, --steps launches of each; "
-                         "motion: only the motion search, --steps launches")
+                         "motion: only the motion search, --steps launches; "
+                         "codec: only the P-frame components and the zero-run coder, --steps launches")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -284,6 +410,14 @@ def main():
     if args.mode == "motion":
         rgb = torch.from_numpy(synth.clip_rgb(FRAMES, H, W, 3)).to("cuda:0")
         print(json.dumps({"mode": "motion", "motion": motion_stage(ycocg_planes(rgb), args.steps)}))
+        return
+
+    if args.mode == "codec":
+        rgb = torch.from_numpy(synth.clip_rgb(FRAMES, H, W, 3)).to("cuda:0")
+        plan = ct.Plan(H, W, J, DIRS, PLANES, "cuda:0")
+        steps_tab = synth.subband_steps(plan.nsub, 3, 3)
+        steps = torch.from_numpy(np.stack([steps_tab[b % 3] for b in range(PLANES)])).to("cuda:0")
+        print(json.dumps({"mode": "codec", "codec": codec_back_end(plan, ycocg_planes(rgb), steps, args.steps)}))
         return
 
     if args.mode == "colour":
@@ -363,41 +497,64 @@ def main():
 
     roofline = None
     kernels = {}
+    step_traffic = None
+    fused_bytes = None
     if not args.no_profile:
         ct.profile_enable(True, 8192)
         for _ in range(args.steps):
             step()
         torch.cuda.synchronize()
-        stats = ct.profile_collect()
+        stats = ct.profile_collect(alg=True)
         ct.profile_enable(False)
         total = sum(v[1] for v in stats.values())
-        for name, (n, tms, by) in stats.items():
-            kernels[name] = {"launches_per_step": n / args.steps, "ms_per_step": tms / args.steps,
-                             "share": tms / total if total else 0.0,
-                             "gbps": by / (tms / 1e3) / 1e9 if tms else 0.0}
+        fused_bytes = sum(v[3] for v in stats.values()) / args.steps
+        step_traffic = 0.0
+        for name, (n, tms, by, al) in stats.items():
+            us = tms / n * 1e3
+            tr = measured_traffic(name)
+            if tr is None:
+                step_traffic = None
+            elif step_traffic is not None:
+                step_traffic += tr * n / args.steps
+            kernels[name] = {"launches_per_step": n / args.steps, "ms_per_step": round(tms / args.steps, 4),
+                             "share": round(tms / total, 4) if total else 0.0, "avg_launch_us": round(us, 2),
+                             "alg_bytes_per_launch": al / n, "compulsory_bytes_per_launch": by / n,
+                             "alg_gbps": round(al / n / (us * 1e3), 1), "compulsory_gbps": round(by / n / (us * 1e3), 1),
+                             "frac_alg": round(al / n / (us * 1e3) / HBM_PEAK_GBPS, 4),
+                             "frac_compulsory": round(by / n / (us * 1e3) / HBM_PEAK_GBPS, 4),
+                             "traffic_bytes_per_launch": tr,
+                             "traffic_over_compulsory": round(tr / (by / n), 3) if tr else None}
         dom = max(stats.items(), key=lambda kv: kv[1][1])
-        name, (n, tms, by) = dom
-        achieved = by / (tms / 1e3) / 1e9
-        traffic = measured_traffic(name, by / n)
+        name, (n, tms, by, al) = dom
+        us = tms / n * 1e3
+        achieved = al / n / (us * 1e3)           # algorithmic bytes per launch / launch time, GB/s
         roofline = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                    "traffic": traffic, "avg_launch_us": round(tms / n * 1e3, 2),
-                    "bytes_per_launch": by / n}
+                    "traffic": measured_traffic(name), "avg_launch_us": round(us, 2),
+                    "alg_bytes_per_launch": al / n, "compulsory_bytes_per_launch": by / n,
+                    "compulsory_achieved": round(by / n / (us * 1e3), 1),
+                    "compulsory_frac": round(by / n / (us * 1e3) / HBM_PEAK_GBPS, 4)}
+
+    copy = None if args.no_extras else copy_ceiling(max(5, args.steps // 2))
 
     batched = None
     if not args.no_batched:
         print("[bench] batched mixed-stream comparison", file=sys.stderr, flush=True)
         batched = batched_comparison(max(3, args.steps // 2))
 
-    print("[bench] colour and K-frame stages", file=sys.stderr, flush=True)
-    fb = front_back_stages(rgb, plan, idx, max(3, args.steps // 2))
-    print("[bench] motion search", file=sys.stderr, flush=True)
-    me = motion_stage(x, max(3, args.steps // 2))
+    fb = me = codec = None
+    if not args.no_extras:
+        print("[bench] colour and K-frame stages", file=sys.stderr, flush=True)
+        fb = front_back_stages(rgb, plan, idx, max(3, args.steps // 2))
+        print("[bench] motion search", file=sys.stderr, flush=True)
+        me = motion_stage(x, max(3, args.steps // 2))
+        print("[bench] codec back end", file=sys.stderr, flush=True)
+        codec = codec_back_end(plan, x, steps, max(3, args.steps // 2))
 
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(rgb_np[0], steps_tab)
+        cpu = cpu_baseline(rgb_np, steps_tab)
 
     out = {
         "metric": METRIC, "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1,
@@ -411,6 +568,13 @@ def main():
         "hbm_effective_gbps": round(eff_gbps, 1),
         "hbm_effective_frac": round(eff_gbps / HBM_PEAK_GBPS, 4),
         "algorithmic_bytes_per_step": alg,
+        "fused_compulsory_bytes_per_step": fused_bytes,
+        "fused_compulsory_frac": round(fused_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4) if fused_bytes else None,
+        "counter_traffic_bytes_per_step": step_traffic,
+        "traffic_over_alg": round(step_traffic / alg, 3) if step_traffic else None,
+        "traffic_over_fused_compulsory": round(step_traffic / fused_bytes, 3) if step_traffic and fused_bytes else None,
+        "copy_ceiling": copy,
+        "hbm_effective_over_copy": round(eff_gbps / copy["gbps"], 4) if copy else None,
         "roundtrip_max_abs_err": err,
         "separate_calls_ms_per_step": round(ms_sep, 4) if ms_sep else None,
         "fused_speedup_vs_separate": round(ms_sep / ms, 3) if ms_sep else None,
@@ -421,6 +585,7 @@ def main():
         "batched": batched,
         "front_back": fb,
         "motion": me,
+        "codec": codec,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -356,6 +356,20 @@ int ct_motion_search(int32_t batch, int32_t height, int32_t width, int32_t w, co
                      const float* prev, int16_t* mv, int32_t* ssd, hipStream_t stream);
 
 /*
+ * Host-only view of ct_motion_search's work layout for search range w
+ * (1..16), as the kernel computes it (for inspection and tests).
+ *   layout  int32 [6] output: LDS row pitch of the window pairs (words), offset
+ *           of the odd-column copy, offset of the block, words per wavefront,
+ *           tasks per window row, and 1 if a full block's last pass runs as
+ *           half-tasks on lane pairs.
+ *   rows,   int32 [cap] outputs: window row and first column offset of the
+ *   sa      first cap tasks (a task is the candidates (row, sa) and
+ *           (row, sa + 2), the second one only when sa + 2 <= 2w).
+ * Returns the number of tasks, or CT_ERR_ARG.
+ */
+int ct_motion_layout_query(int32_t w, int32_t* layout, int32_t* rows, int32_t* sa, int32_t cap);
+
+/*
  * P-frame components (paper section 3.7): the motion-compensated prediction
  * is made on the quantised CT components, with the luminance motion vectors
  * of ct_motion_search mapped to each component's scale. Conventions as

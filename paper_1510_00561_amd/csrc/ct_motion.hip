@@ -178,12 +178,13 @@ __global__ __launch_bounds__(NT) void motion_search_kernel(MotionArgs a) {
     // sc mod 4 in {0, 1}, paired with sc + 2; tpr tasks per row cover every
     // sc in [0, 2w] once.
     const bool full = bh == kB && bw == kB;   // wave-uniform
-    const int side = 2 * w + 1, tpr = 2 * (side / 4) + min(side % 4, 2), nt = side * tpr;
+    const int nt = motion_tasks(w);
     // A full block whose last pass would hold at most 32 tasks runs that pass
     // as 2 x tail half-tasks instead: lanes 2i and 2i + 1 take rows 0-7 and
     // 8-15 of task i and add their sums across the lane pair.
-    const int nfull = nt / 64, tail = nt - 64 * nfull;
-    const bool split = full && tail > 0 && tail <= 32;
+    int nfull, tail;
+    bool split;
+    motion_passes(w, full, &nfull, &tail, &split);
     const int npass = split ? nfull : (nt + 63) / 64;
     uint64_t best = ~uint64_t(0);
     auto consider = [&](bool live, int dy, int sa, int ssd_a, int ssd_b) {
@@ -196,8 +197,9 @@ __global__ __launch_bounds__(NT) void motion_search_kernel(MotionArgs a) {
     };
     for (int p = 0; p < npass; ++p) {
         const int t0 = 64 * p;
-        const int t = min(t0 + lane, nt - 1), row = t / tpr, u = t - row * tpr;
-        const int dy = row - w, sa = 4 * (u >> 1) + (u & 1);
+        int row, sa;
+        motion_task(w, min(t0 + lane, nt - 1), &row, &sa);
+        const int dy = row - w;
         const bool live = t0 + lane < nt && y0 + dy >= 0 && y0 + dy + bh <= a.H;
         const uint32_t* ref = (sa & 1) ? odd : even;
         int ssd_a, ssd_b;
@@ -207,8 +209,9 @@ __global__ __launch_bounds__(NT) void motion_search_kernel(MotionArgs a) {
     }
     if (split) {
         const int i = min(lane >> 1, tail - 1), h = lane & 1;
-        const int t = 64 * nfull + i, row = t / tpr, u = t - row * tpr;
-        const int dy = row - w, sa = 4 * (u >> 1) + (u & 1);
+        int row, sa;
+        motion_task(w, 64 * nfull + i, &row, &sa);
+        const int dy = row - w;
         const bool live = (lane >> 1) < tail && y0 + dy >= 0 && y0 + dy + bh <= a.H;
         const uint32_t* ref = (sa & 1) ? odd : even;
         int ssd_a, ssd_b;

@@ -45,4 +45,24 @@ int ct_motion_search(int32_t batch, int32_t height, int32_t width, int32_t w, co
     return CT_OK;
 }
 
+int ct_motion_layout_query(int32_t w, int32_t* layout, int32_t* rows, int32_t* sa, int32_t cap) {
+    if (w < 1 || w > ct::kMotionMaxW || !layout || cap < 0 || (cap > 0 && (!rows || !sa))) return CT_ERR_ARG;
+    ct::MotionArgs a;
+    memset(&a, 0, sizeof(a));
+    a.w = w;
+    ct::motion_layout(&a);
+    int nfull, tail;
+    bool split;
+    ct::motion_passes(w, true, &nfull, &tail, &split);
+    layout[0] = a.rp;
+    layout[1] = a.odd_off;
+    layout[2] = a.cur_off;
+    layout[3] = a.lds_per_wave;
+    layout[4] = ct::motion_tasks_per_row(w);
+    layout[5] = split ? 1 : 0;
+    const int nt = ct::motion_tasks(w);
+    for (int t = 0; t < nt && t < cap; ++t) ct::motion_task(w, t, rows + t, sa + t);
+    return nt;
+}
+
 }  // extern "C"

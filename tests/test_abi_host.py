@@ -117,6 +117,11 @@ def test_fault_injection_hook(ct, monkeypatch):
     assert lib.ct_ycocg_to_rgb(1, 4, 4, 2, dummy, dummy, dummy, dummy, None) == -4
     assert lib.ct_lowpass_diff(ctypes.byref(g), 1, dummy, 1, None) == -4
     assert lib.ct_motion_search(1, 16, 16, 8, dummy, dummy, dummy, None, None) == -4
+    other = ctypes.c_void_p(0x2000)
+    assert lib.ct_mc_residual(ctypes.byref(g), 1, 1, dummy, dummy, dummy, 16, 16, 1, 0, other, None) == -4
+    n = ctypes.c_size_t(0)
+    assert lib.ct_rle_workspace_bytes(ctypes.byref(g), 1, ctypes.byref(n)) == 0
+    assert lib.ct_rle_encode(ctypes.byref(g), 1, dummy, 0, dummy, dummy, dummy, n.value, None) == -4
     assert lib.ct_strerror(-4) == b"HIP runtime error"
 
 
