@@ -1,13 +1,13 @@
 // P-frame motion compensation (paper section 3.7) and zero-run coding
 // (section 3.8) of the quantised CT components, for gfx950.
 //
-// Motion compensation is one pass over the indices: every element finds its
-// component and natural position (i, k), the 16 x 16 block of the luminance
-// pixel it sits on, that block's vector mapped to the component's sample
-// spacing (rounded, halves away from zero), and subtracts (or, for the
-// decoder, adds) the previous plane's element at the displaced position,
+// Motion compensation is one pass over the indices, one wavefront per stored
+// row of a component: every element finds the 16 x 16 block of the
+// luminance pixel it sits on, that block's vector mapped to the component's
+// sample spacing (rounded, halves away from zero), and subtracts (or, for
+// the decoder, adds) the previous plane's element at the displaced position,
 // modulo the component's size and modulo 2^16. HBM-bound: 2 bytes read,
-// 2 gathered (mostly within the lines of the same row) and 2 written per
+// 2 gathered (mostly within the lines of nearby rows) and 2 written per
 // element.
 //
 // The zero-run coder is a stream compaction in three passes:
@@ -36,12 +36,6 @@ __device__ __forceinline__ int pmod(int a, int n) {
     return r < 0 ? r + n : r;
 }
 
-// a / b rounded to the nearest integer, halves away from zero (b > 0)
-__device__ __forceinline__ int round_div(int a, int b) {
-    const int q = (2 * abs(a) + b) / (2 * b);
-    return a < 0 ? -q : q;
-}
-
 // Storage position p (0 = lowpass, then levels J..1) -> level index (0 =
 // lowpass, else the LP level j).
 __device__ __forceinline__ int level_of_pos(const LevelTable& T, int p) { return p == 0 ? 0 : T.J + 1 - p; }
@@ -52,61 +46,160 @@ __device__ __forceinline__ int find_pos(const LevelTable& T, int64_t e) {
     return p;
 }
 
-__global__ __launch_bounds__(NT) void mc_kernel(MCArgs A) {
-    const LevelTable& T = A.T;
-    const int64_t gid = int64_t(blockIdx.x) * NT + threadIdx.x;
-    if (gid >= int64_t(A.batch) * T.ncoef) return;
-    const int b = int(gid / T.ncoef);
-    const int64_t e = gid - int64_t(b) * T.ncoef;
-    const int p = find_pos(T, e);
+// floor(x / b) for 0 <= x < 2^22 and 1 <= b < 2^22, with rb = 1/b: the float
+// quotient is within one of the true one, and one correction each way makes
+// it exact.
+__device__ __forceinline__ int udiv_small(int x, int b, float rb) {
+    int q = int(float(x) * rb);
+    if ((q + 1) * b <= x) ++q;
+    if (q * b > x) --q;
+    return q;
+}
+
+// a / b rounded to the nearest integer, halves away from zero: floor((2|a| +
+// b) / (2b)) with the sign of a (|a| <= 32768, b < 2^20).
+__device__ __forceinline__ int round_div_fast(int a, int b2, float rb2) {
+    const int q = udiv_small(2 * abs(a) + (b2 >> 1), b2, rb2);
+    return a < 0 ? -q : q;
+}
+
+// (t mod n) for the displaced index t of an element, usually within one
+// period of the component.
+__device__ __forceinline__ int wrap(int t, int n) {
+    if (t >= 0 && t < n) return t;
+    if (t < 0 && t >= -n) return t + n;
+    if (t >= n && t < 2 * n) return t - n;
+    return pmod(t, n);
+}
+
+// One wavefront per stored row of one component of one plane. The row's
+// component, its natural row (or, for the transposed vertical-cone subbands,
+// natural column), the sample spacing and the block row (column) are the
+// same for the whole wavefront; lanes step along the row.
+struct MCItem {
+    int64_t start;      // first element of the stored row within the plane
+    int len;            // elements along the stored row
+    bool tr;            // transposed subband: the row is a natural column
+    int fixed;          // natural row (row-major) or natural column (transposed)
+    int rows, cols;     // natural size of the component
+    int f, s1, s2, o1, o2;   // pixel = f (o + s (i, k))
+    int64_t base;       // first element of the component
+};
+
+__device__ MCItem mc_item(const LevelTable& T, const int* item0, int it, int n, bool* ok) {
+    MCItem m;
+    int p = 0;
+    while (p <= T.J && it >= item0[p + 1]) ++p;
+    *ok = p <= T.J;
+    if (!*ok) return m;
     const int lv = level_of_pos(T, p);
-    const int local = int(e - T.off[p]);
-    int i, k, rows, cols, py, px, sy, sx;
-    bool tr = false;
-    int64_t base = T.off[p];
+    int w = it - item0[p];
+    m.tr = false;
     if (lv == 0) {
-        rows = T.R >> T.J;
-        cols = T.C >> T.J;
-        i = local / cols;
-        k = local - i * cols;
-        sy = sx = A.n << T.J;
-        py = sy * i;
-        px = sx * k;
-    } else {
-        const int sz = T.rows_h[lv] * T.cols_h[lv];
-        const int kk = local / sz, w = local - kk * sz;
-        const int f = A.n << (lv - 1);
-        int s1, s2;
-        if (kk < T.nh[lv]) {
-            rows = T.rows_h[lv];
-            cols = T.cols_h[lv];
-            i = w / cols;
-            k = w - i * cols;
-            s1 = 1 << T.lsh1_h[lv];
-            s2 = 1 << T.lsh2_h[lv];
-        } else {
-            rows = T.rows_v[lv];
-            cols = T.cols_v[lv];
-            k = w / rows;
-            i = w - k * rows;
-            tr = true;
-            s1 = 1 << T.lsh1_v[lv];
-            s2 = 1 << T.lsh2_v[lv];
-        }
-        base += int64_t(kk) * sz;
-        py = f * (T.o1[lv][kk] + s1 * i);
-        px = f * (T.o2[lv][kk] + s2 * k);
-        sy = f * s1;
-        sx = f * s2;
+        m.rows = T.R >> T.J;
+        m.cols = T.C >> T.J;
+        m.base = 0;
+        m.fixed = w;
+        m.start = int64_t(w) * m.cols;
+        m.len = m.cols;
+        m.f = n << T.J;
+        m.s1 = m.s2 = 1;
+        m.o1 = m.o2 = 0;
+        return m;
     }
-    const int by = min(py >> 4, A.nby - 1), bx = min(px >> 4, A.nbx - 1);
-    const int16_t* v = A.mv + ((int64_t(b / A.group) * A.nby + by) * A.nbx + bx) * 2;
-    const int i2 = pmod(i + round_div(v[0], sy), rows);
-    const int k2 = pmod(k + round_div(v[1], sx), cols);
-    const int64_t src = base + (tr ? int64_t(k2) * rows + i2 : int64_t(i2) * cols + k2);
-    const int pv = A.prev[int64_t(b) * T.ncoef + src];
-    const int cv = A.cur[gid];
-    A.out[gid] = int16_t(A.inverse ? cv + pv : cv - pv);   // modulo 2^16
+    const int sz = T.rows_h[lv] * T.cols_h[lv];
+    const int nhr = T.nh[lv] * T.rows_h[lv];
+    m.f = n << (lv - 1);
+    int kk;
+    if (w < nhr) {
+        kk = w / T.rows_h[lv];
+        const int i = w - kk * T.rows_h[lv];
+        m.rows = T.rows_h[lv];
+        m.cols = T.cols_h[lv];
+        m.fixed = i;
+        m.len = m.cols;
+        m.s1 = 1 << T.lsh1_h[lv];
+        m.s2 = 1 << T.lsh2_h[lv];
+        m.base = T.off[p] + int64_t(kk) * sz;
+        m.start = m.base + int64_t(i) * m.cols;
+    } else {
+        w -= nhr;
+        const int kv = w / T.cols_v[lv], k = w - kv * T.cols_v[lv];
+        kk = T.nh[lv] + kv;
+        m.tr = true;
+        m.rows = T.rows_v[lv];
+        m.cols = T.cols_v[lv];
+        m.fixed = k;
+        m.len = m.rows;
+        m.s1 = 1 << T.lsh1_v[lv];
+        m.s2 = 1 << T.lsh2_v[lv];
+        m.base = T.off[p] + int64_t(kk) * sz;
+        m.start = m.base + int64_t(k) * m.rows;
+    }
+    m.o1 = T.o1[lv][kk];
+    m.o2 = T.o2[lv][kk];
+    return m;
+}
+
+struct MCItems {
+    int item0[kMaxLevels + 3];
+};
+
+MCItems mc_items_of(const LevelTable& T) {
+    MCItems it;
+    it.item0[0] = 0;
+    for (int p = 0; p <= T.J; ++p) {
+        const int lv = p == 0 ? 0 : T.J + 1 - p;
+        const int n = lv == 0 ? (T.R >> T.J)
+                              : T.nh[lv] * T.rows_h[lv] + (T.nsub_l[lv] - T.nh[lv]) * T.cols_v[lv];
+        it.item0[p + 1] = it.item0[p] + n;
+    }
+    for (int p = T.J + 2; p < kMaxLevels + 3; ++p) it.item0[p] = it.item0[T.J + 1];
+    return it;
+}
+
+__global__ __launch_bounds__(NT) void mc_kernel(MCArgs A, MCItems IT) {
+    const LevelTable& T = A.T;
+    const int per = IT.item0[T.J + 1];
+    const int gw = __builtin_amdgcn_readfirstlane(int(blockIdx.x) * (NT / 64) + int(threadIdx.x >> 6));
+    if (gw >= per * A.batch) return;
+    const int b = gw / per;
+    bool ok;
+    const MCItem m = mc_item(T, IT.item0, gw - b * per, A.n, &ok);
+    if (!ok) return;
+    const int lane = threadIdx.x & 63;
+    const int16_t* cur = A.cur + int64_t(b) * T.ncoef;
+    const int16_t* prev = A.prev + int64_t(b) * T.ncoef;
+    int16_t* out = A.out + int64_t(b) * T.ncoef;
+    const int16_t* mv = A.mv + int64_t(b / A.group) * A.nby * A.nbx * 2;
+    const int sy = m.f * m.s1, sx = m.f * m.s2;            // sample spacing in pixels
+    const float rby = 1.f / float(2 * sy), rbx = 1.f / float(2 * sx);
+    // the fixed coordinate's block and pixel
+    const int fixed_px = m.f * ((m.tr ? m.o2 : m.o1) + (m.tr ? m.s2 : m.s1) * m.fixed);
+    const int fixed_blk = m.tr ? min(fixed_px >> 4, A.nbx - 1) : min(fixed_px >> 4, A.nby - 1);
+    for (int e = lane; e < m.len; e += 64) {
+        // the varying coordinate: natural column (row-major) or row (transposed)
+        const int px = m.f * ((m.tr ? m.o1 : m.o2) + (m.tr ? m.s1 : m.s2) * e);
+        int by, bx, i, k;
+        if (m.tr) {
+            by = min(px >> 4, A.nby - 1);
+            bx = fixed_blk;
+            i = e;
+            k = m.fixed;
+        } else {
+            by = fixed_blk;
+            bx = min(px >> 4, A.nbx - 1);
+            i = m.fixed;
+            k = e;
+        }
+        const int16_t* v = mv + (by * A.nbx + bx) * 2;
+        const int i2 = wrap(i + round_div_fast(v[0], 2 * sy, rby), m.rows);
+        const int k2 = wrap(k + round_div_fast(v[1], 2 * sx, rbx), m.cols);
+        const int64_t src = m.base + (m.tr ? int64_t(k2) * m.rows + i2 : int64_t(i2) * m.cols + k2);
+        const int pv = prev[src];
+        const int cv = cur[m.start + e];
+        out[m.start + e] = int16_t(A.inverse ? cv + pv : cv - pv);   // modulo 2^16
+    }
 }
 
 // ---------------------------------------------------------------- zero runs
@@ -371,9 +464,10 @@ ItemTable items_of(const LevelTable& T) {
 }  // namespace
 
 hipError_t launch_mc(const MCArgs& a, hipStream_t st) {
-    const int64_t total = int64_t(a.batch) * a.T.ncoef;
-    if (total == 0) return hipSuccess;
-    mc_kernel<<<unsigned((total + NT - 1) / NT), NT, 0, st>>>(a);
+    if (a.batch == 0) return hipSuccess;
+    const MCItems it = mc_items_of(a.T);
+    const int64_t waves = int64_t(it.item0[a.T.J + 1]) * a.batch;
+    mc_kernel<<<unsigned((waves + NT / 64 - 1) / (NT / 64)), NT, 0, st>>>(a, it);
     return hipGetLastError();
 }
 

@@ -29,24 +29,25 @@ def _idx(table, B, seed, density=1.0, lo=-32768, hi=32767):
 
 
 MC_CASES = [
-    (64, 96, 2, [8, 4], 2, 1, 1),
-    (70, 90, 3, [16, 8, 4], 3, 1, 3),       # padded; three planes share one vector field
-    (64, 96, 2, [4, 32], 2, 2, 1),          # chroma factor 2
-    (40, 40, 3, [8, 4, 4], 3, 4, 1),        # odd coefficient count, factor 4
-    (128, 128, 1, [64], 1, 1, 1),
-    (240, 320, 4, [8, 8, 8, 8], 3, 1, 3),
+    (64, 96, 2, [8, 4], 2, 1, 1, 16),
+    (70, 90, 3, [16, 8, 4], 2, 3, 1, 32767),  # vectors far beyond a component's size, factor 3
+    (70, 90, 3, [16, 8, 4], 3, 1, 3, 16),   # padded; three planes share one vector field
+    (64, 96, 2, [4, 32], 2, 2, 1, 16),      # chroma factor 2
+    (40, 40, 3, [8, 4, 4], 3, 4, 1, 16),    # odd coefficient count, factor 4
+    (128, 128, 1, [64], 1, 1, 1, 16),
+    (240, 320, 4, [8, 8, 8, 8], 3, 1, 3, 16),
 ]
 
 
-@pytest.mark.parametrize("H,W,J,dirs,B,n,group", MC_CASES)
-def test_mc_residual_bit_exact(H, W, J, dirs, B, n, group):
-    print(f"[codec] mc {H}x{W} J={J} dirs={dirs} B={B} n={n} group={group}", flush=True)
+@pytest.mark.parametrize("H,W,J,dirs,B,n,group,vmax", MC_CASES)
+def test_mc_residual_bit_exact(H, W, J, dirs, B, n, group, vmax):
+    print(f"[codec] mc {H}x{W} J={J} dirs={dirs} B={B} n={n} group={group} |v| <= {vmax}", flush=True)
     table = geo.subband_table(H, W, J, dirs)
     plan = _plan(H, W, J, dirs, B)
     cur, prev = _idx(table, B, 1), _idx(table, B, 2)
     nby, nbx = -(-H * n // 16), -(-W * n // 16)
     rng = np.random.default_rng(3)
-    mv = rng.integers(-16, 17, size=(-(-B // group), nby, nbx, 2)).astype(np.int16)
+    mv = rng.integers(-vmax, vmax + 1, size=(-(-B // group), nby, nbx, 2)).astype(np.int16)
     cd, pd, md = (torch.from_numpy(a).cuda() for a in (cur, prev, mv))
     res = plan.mc_residual(cd, pd, md, n=n, group=group).cpu().numpy()
     for b in range(B):

@@ -151,6 +151,52 @@ def test_quantiser_ties_and_limits():
     assert list(idx_h[0, table[1].offset:table[1].offset + len(vals)]) == [1, 2, 3, -1, -3, 0, 32767, -32768, 4]
 
 
+def _near_half_integers(table, steps, B, seed):
+    """Coefficients at and a few float32 steps around (k + 1/2) * step for every
+    directional subband, k up to the int16 range: the values whose index
+    depends on the quotient's last bit and on the direction of the tie rule."""
+    rng = np.random.default_rng(seed)
+    n = table[-1].offset + table[-1].size
+    c = rng.uniform(-300, 300, (B, n)).astype(np.float32)
+    for s, sb in enumerate(table):
+        if s == 0:
+            continue
+        m = sb.size
+        k = rng.integers(-32800, 32800, size=(B, m)).astype(np.float64)
+        k[:, : m // 2] = rng.integers(-40, 40, size=(B, m // 2))
+        base = ((k + 0.5) * np.float64(steps[s])).astype(np.float32)
+        ulps = rng.integers(-3, 4, size=(B, m))
+        v = base.copy()
+        for _ in range(3):
+            up = ulps > 0
+            down = ulps < 0
+            v = np.where(up, np.nextafter(v, np.float32(np.inf)), v)
+            v = np.where(down, np.nextafter(v, np.float32(-np.inf)), v)
+            ulps = ulps - np.sign(ulps)
+        c[:, sb.offset:sb.offset + m] = v
+    return c
+
+
+@pytest.mark.parametrize("case", ["integer", "fractional", "extreme"])
+def test_quantiser_near_half_integers(case):
+    H, W, J, dirs, B = 64, 96, 2, [4, 32], 3
+    table = geo.subband_table(H, W, J, dirs)
+    rng = np.random.default_rng({"integer": 1, "fractional": 2, "extreme": 3}[case])
+    if case == "integer":
+        steps = rng.integers(3, 65, size=len(table)).astype(np.float32)
+    elif case == "fractional":
+        steps = rng.choice(np.array([0.1, 0.37, 7.5, 1e-3, 13.25, 0.0625], np.float32), size=len(table))
+    else:   # steps near the float32 exponent limits
+        steps = rng.choice(np.array([2.0 ** -101, 2.0 ** 101, 3.0, 2.0 ** -99], np.float32), size=len(table))
+    c = _near_half_integers(table, steps, B, 7)
+    plan = _plan(H, W, J, dirs, B)
+    idx, side = plan.quantize(_dev(c), _dev(steps))
+    idx_h = idx.cpu().numpy()
+    for b in range(B):
+        q_ref, _ = oq.quantize32(c[b], steps, table)
+        np.testing.assert_array_equal(idx_h[b], q_ref)
+
+
 def test_quantise_gpu_coefficients_mismatch_rate():
     """Indices from the GPU's own coefficients differ only at rounding boundaries."""
     H, W, J, dirs = 256, 256, 2, [8, 4]
