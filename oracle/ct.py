@@ -23,6 +23,13 @@ in reverse order with every stage transposed:
     self-adjoint and E, O are orthogonal projections;
   * padding by reflection transposes to folding the mirrored rows and
     columns back onto their sources; cropping transposes to zero padding.
+
+Variants (not the paper's choice; section 2.1 names the 9-7 pair and the
+LP's usual reconstruction is not specified beyond perfect reconstruction):
+every function takes `filters` ('97' the paper's pair, '53' the LeGall 5/3
+pair, filters.py) and the inverse and its adjoint take `recon` ('dual' the
+dual-frame LP synthesis, 'ba' the Burt-Adelson one, lp.py). The forward
+transform and its adjoint do not depend on `recon`.
 """
 import numpy as np
 
@@ -50,10 +57,17 @@ def _pad_adjoint(y, H, W):
     return out
 
 
-def _filters():
-    p, q = filters.cdf97_polynomials()
-    hbar, gbar = filters.lp_filters()
+def _filters(kind='97'):
+    p, q = filters.polynomials(kind)
+    hbar, gbar = filters.lp_filters(kind)
     return p, q, hbar, gbar
+
+
+RECONS = ('dual', 'ba')
+
+
+def _neg(poly):
+    return filters.negate_argument(poly)
 
 
 def pack(lowpass, levels_subbands, table):
@@ -83,62 +97,67 @@ def unpack(vec, table, levels):
     return lowpass, subs
 
 
-def forward(x, levels, dirs):
+def forward(x, levels, dirs, filters='97'):
     """Forward CT of one H x W plane; returns the packed FP64 coefficient vector."""
     x = np.asarray(x, dtype=np.float64)
     H, W = x.shape
     table = geo.subband_table(H, W, levels, dirs)
     R, C = geo.padded_size(H, W, levels, dirs)
-    p, q, hbar, gbar = _filters()
+    p, q, hbar, gbar = _filters(filters)
     c = _pad(x, R, C)
     subs = []
     for j in range(1, levels + 1):
         c, d = lp.lp_analysis(c, hbar, gbar)
         l = geo.log2_exact(dirs[j - 1])
-        subs.append(dfb.dfb_analysis(d, l, p, filters.negate_argument(q)))
+        subs.append(dfb.dfb_analysis(d, l, p, _neg(q)))
     return pack(c, subs, table)
 
 
-def inverse(vec, height, width, levels, dirs):
+def inverse(vec, height, width, levels, dirs, filters='97', recon='dual'):
     """Inverse CT of one packed coefficient vector; returns the H x W plane."""
+    assert recon in RECONS
     table = geo.subband_table(height, width, levels, dirs)
     R, C = geo.padded_size(height, width, levels, dirs)
-    p, q, hbar, gbar = _filters()
+    p, q, hbar, gbar = _filters(filters)
     c, subs = unpack(vec, table, levels)
     for j in range(levels, 0, -1):
         Rj, Cj = geo.level_size(R, C, j)
         l = geo.log2_exact(dirs[j - 1])
-        d = dfb.dfb_synthesis(subs[j - 1], l, (Rj, Cj), q, filters.negate_argument(p))
-        c = lp.lp_synthesis(c, d, hbar, gbar)
+        d = dfb.dfb_synthesis(subs[j - 1], l, (Rj, Cj), q, _neg(p))
+        c = lp.lp_synthesis(c, d, hbar, gbar) if recon == 'dual' else lp.lp_synthesis_ba(c, d, gbar)
     return c[:height, :width].copy()
 
 
-def forward_adjoint(gvec, height, width, levels, dirs):
+def forward_adjoint(gvec, height, width, levels, dirs, filters='97'):
     """Transpose of forward: maps a coefficient-space vector to an H x W plane."""
     table = geo.subband_table(height, width, levels, dirs)
     R, C = geo.padded_size(height, width, levels, dirs)
-    p, q, hbar, gbar = _filters()
+    p, q, hbar, gbar = _filters(filters)
     c, subs = unpack(gvec, table, levels)
     for j in range(levels, 0, -1):
         Rj, Cj = geo.level_size(R, C, j)
         l = geo.log2_exact(dirs[j - 1])
-        d = dfb.dfb_synthesis(subs[j - 1], l, (Rj, Cj), p, filters.negate_argument(q))
+        d = dfb.dfb_synthesis(subs[j - 1], l, (Rj, Cj), p, _neg(q))
         # transpose of LP analysis (hbar, gbar) = LP synthesis (gbar, hbar)
         c = lp.lp_synthesis(c, d, gbar, hbar)
     return _pad_adjoint(c, height, width)
 
 
-def inverse_adjoint(gplane, height, width, levels, dirs):
+def inverse_adjoint(gplane, height, width, levels, dirs, filters='97', recon='dual'):
     """Transpose of inverse: maps an H x W plane to a coefficient-space vector."""
+    assert recon in RECONS
     table = geo.subband_table(height, width, levels, dirs)
     R, C = geo.padded_size(height, width, levels, dirs)
-    p, q, hbar, gbar = _filters()
+    p, q, hbar, gbar = _filters(filters)
     c = np.zeros((R, C))
     c[:height, :width] = np.asarray(gplane, dtype=np.float64)
     subs = []
     for j in range(1, levels + 1):
-        # transpose of dual LP synthesis (hbar, gbar) = LP analysis (gbar, hbar)
-        c, d = lp.lp_analysis(c, gbar, hbar)
+        if recon == 'dual':
+            # transpose of dual LP synthesis (hbar, gbar) = LP analysis (gbar, hbar)
+            c, d = lp.lp_analysis(c, gbar, hbar)
+        else:
+            c, d = lp.lp_synthesis_ba_adjoint(c, gbar)
         l = geo.log2_exact(dirs[j - 1])
-        subs.append(dfb.dfb_analysis(d, l, q, filters.negate_argument(p)))
+        subs.append(dfb.dfb_analysis(d, l, q, _neg(p)))
     return pack(c, subs, table)

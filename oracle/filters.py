@@ -83,15 +83,43 @@ def cdf97_taps():
     return poly_to_taps(p), poly_to_taps(q)
 
 
-def lp_filters():
+def legall53_polynomials():
+    """Return (p, q) of the LeGall 5/3 pair, lowest degree first, in t = cos(w).
+
+    A variant filter pair (not the paper's): the same construction as the
+    9-7 pair with two zeros at w = pi on each side instead of four. The
+    Daubechies halfband product with two zeros at pi has the remainder
+    polynomial Q(y) = 1 + 2y; the synthesis lowpass takes cos^2(w/2) alone
+    and the analysis lowpass cos^2(w/2) Q(y), both normalised to sqrt(2) at
+    t = 1:
+      p(t) = h(w), degree 2 (5 taps);   q(t) = g(w), degree 1 (3 taps).
+    """
+    half_plus = np.array([0.5, 0.5])              # cos^2(w/2) = (1 + t)/2
+    remainder = np.array([2.0, -1.0])             # 1 + 2y with y = (1 - t)/2
+    p = npoly.polymul(half_plus, remainder)
+    q = half_plus.copy()
+    p = p * (np.sqrt(2.0) / npoly.polyval(1.0, p))
+    q = q * (np.sqrt(2.0) / npoly.polyval(1.0, q))
+    return p, q
+
+
+FILTERS = {'97': cdf97_polynomials, '53': legall53_polynomials}
+
+
+def polynomials(kind='97'):
+    """(p, q) of filter pair `kind`: '97' (the paper's 9-7) or '53' (LeGall 5/3)."""
+    return FILTERS[kind]()
+
+
+def lp_filters(kind='97'):
     """LP filters of the unit-DC reading (O-3 of the contourlet reading).
 
     hbar = h / sqrt(2) sums to 1 (the 2-D lowpass keeps the pixel scale),
     gbar = g * sqrt(2) sums to 2 (so that gbar applied to an upsampled
     constant returns the constant). Both are centred: index len//2 is tap 0.
     """
-    h, g = cdf97_taps()
-    return h / np.sqrt(2.0), g * np.sqrt(2.0)
+    p, q = polynomials(kind)
+    return poly_to_taps(p) / np.sqrt(2.0), poly_to_taps(q) * np.sqrt(2.0)
 
 
 def negate_argument(poly):

@@ -16,6 +16,17 @@ Reading (unit-DC LP): with hbar = h / sqrt(2) (sum 1) and gbar = g * sqrt(2)
 Synthesis is exact on unquantised coefficients because down2 hbar gbar up2 is
 the identity (biorthogonality of the 9-7 pair).
 
+Variant (not the paper's choice): the original Burt-Adelson reconstruction
+skips the correction of c,
+
+  synthesis (BA)  x = d + gbar * up2(c)
+
+and is exact on unquantised coefficients for the same reason (d is then
+exactly x - gbar * up2(c)). It differs from the dual-frame reconstruction
+only where c and d are not consistent, e.g. after quantisation: an error in d
+passes into x unchanged, while the dual frame removes its part that the
+lowpass channel sees.
+
 The functions below are generic in the two filters (`lo`, `up`): the forward
 transform passes (hbar, gbar). The adjoints of both directions are the same
 operations with the filters swapped (see ct.py).
@@ -66,3 +77,19 @@ def lp_synthesis(c, d, lo, up):
     d = np.asarray(d, dtype=np.float64)
     c_corr = np.asarray(c, dtype=np.float64) - down2(filter2(d, lo))
     return d + filter2(up2(c_corr), up)
+
+
+def lp_synthesis_ba(c, d, up):
+    """One Burt-Adelson LP synthesis level: x = d + up * up2(c)."""
+    return np.asarray(d, dtype=np.float64) + filter2(up2(np.asarray(c, dtype=np.float64)), up)
+
+
+def lp_synthesis_ba_adjoint(x, up):
+    """Transpose of lp_synthesis_ba: returns (c, d) = (down2(up * x), x).
+
+    filter2 with symmetric taps is self-adjoint and down2 is the transpose of
+    up2, so the c part is a lowpass analysis with the synthesis filter; the d
+    part is the identity.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    return down2(filter2(x, up)), x.copy()

@@ -62,10 +62,16 @@ def lp_matrices(R, C, lo, up):
     return Hc, np.eye(R * C) - Ug @ Hc
 
 
-def lp_synthesis_matrices(R, C, lo, up):
-    """(S_c, S_d): dual LP synthesis x = S_c c + S_d d."""
+def lp_synthesis_matrices(R, C, lo, up, recon='dual'):
+    """(S_c, S_d): LP synthesis x = S_c c + S_d d.
+
+    Dual frame: x = U c + (I - U H) d, U the upsampling filter and H the
+    decimating lowpass. Burt-Adelson: x = U c + d.
+    """
     Hd = np.kron(decimation(R) @ circulant(lo, R), decimation(C) @ circulant(lo, C))
     Ug = np.kron(circulant(up, R) @ decimation(R).T, circulant(up, C) @ decimation(C).T)
+    if recon == 'ba':
+        return Ug, np.eye(R * C)
     return Ug, np.eye(R * C) - Ug @ Hd
 
 
@@ -184,10 +190,10 @@ def dfb_matrix(R, C, l, f0, f1):
     return np.vstack(rows)
 
 
-def forward_matrix(H, W, R, C, levels, dirs):
-    """Dense matrix of the forward CT on an H x W frame."""
-    p, q = filters.cdf97_polynomials()
-    hbar, gbar = filters.lp_filters()
+def forward_matrix(H, W, R, C, levels, dirs, kind='97'):
+    """Dense matrix of the forward CT on an H x W frame (filter pair `kind`)."""
+    p, q = filters.polynomials(kind)
+    hbar, gbar = filters.lp_filters(kind)
     q_neg = filters.negate_argument(q)
     M = pad_matrix(H, W, R, C)
     blocks = []
@@ -200,10 +206,10 @@ def forward_matrix(H, W, R, C, levels, dirs):
     return np.vstack([M] + blocks[::-1])
 
 
-def inverse_matrix(H, W, R, C, levels, dirs):
+def inverse_matrix(H, W, R, C, levels, dirs, kind='97', recon='dual'):
     """Dense matrix of the inverse CT (coefficients -> H x W frame)."""
-    p, q = filters.cdf97_polynomials()
-    hbar, gbar = filters.lp_filters()
+    p, q = filters.polynomials(kind)
+    hbar, gbar = filters.lp_filters(kind)
     p_neg = filters.negate_argument(p)
     # DFB synthesis is the exact inverse of analysis; build it as the
     # synthesis polynomial pair applied through the transpose structure:
@@ -228,7 +234,7 @@ def inverse_matrix(H, W, R, C, levels, dirs):
         Ssyn = dfb_matrix(Rj, Cj, l, q, p_neg).T
         Dd = np.zeros((Rj * Cj, ncoef))
         Dd[:, offs[j]:offs[j] + band_n[j]] = Ssyn
-        Sc, Sd = lp_synthesis_matrices(Rj, Cj, hbar, gbar)
+        Sc, Sd = lp_synthesis_matrices(Rj, Cj, hbar, gbar, recon)
         Xc = Sc @ Xc + Sd @ Dd
     crop = np.zeros((H * W, R * C))
     for r in range(H):
