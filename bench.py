@@ -542,6 +542,25 @@ def main():
         print("[bench] batched mixed-stream comparison", file=sys.stderr, flush=True)
         batched = batched_comparison(max(3, args.steps // 2))
 
+    variants = None
+    if not args.no_extras:
+        # the same fused step with the variant filter pair and reconstruction
+        print("[bench] variant filters and reconstruction", file=sys.stderr, flush=True)
+        variants = {}
+        for f, r in (("53", "dual"), ("97", "ba"), ("53", "ba")):
+            vp = ct.Plan(H, W, J, DIRS, PLANES, "cuda:0", filters=f, recon=r)
+            vrec = torch.empty_like(x)
+
+            def vstep():
+                vp.encode(x, steps, idx2, side2)
+                vp.decode(idx2, steps, side2, out=vrec)
+            vms, _ = timed(vstep)
+            variants[f"{f}_{r}"] = {"filters": {"97": "CDF 9-7", "53": "LeGall 5/3"}[f],
+                                    "recon": {"dual": "dual frame", "ba": "Burt-Adelson"}[r],
+                                    "ms_per_step": round(vms, 4), "frames_per_s": round(FRAMES / (vms / 1e3), 1),
+                                    "roundtrip_max_abs_err": float((vrec - x).abs().max())}
+            del vp, vrec
+
     fb = me = codec = None
     if not args.no_extras:
         print("[bench] colour and K-frame stages", file=sys.stderr, flush=True)
@@ -583,6 +602,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "batched": batched,
+        "variants": variants,
         "front_back": fb,
         "motion": me,
         "codec": codec,

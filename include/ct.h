@@ -61,12 +61,33 @@ enum {
  *                  finest level. Each a power of two in [4, 64] (2^l wedges
  *                  at DFB level l, section 2.1). Entries at j >= levels are
  *                  ignored.
+ *   filters        CT_FILTERS_CDF97 (0): the 9-7 pair of section 2.1 for the
+ *                  LP and the fan filters of the DFB. CT_FILTERS_LEGALL53
+ *                  (1): the LeGall 5/3 pair in both places, a variant (same
+ *                  construction with two zeros at pi instead of four).
+ *   recon          CT_RECON_DUAL (0): the dual-frame LP synthesis, which
+ *                  removes the part of a bandpass error the lowpass channel
+ *                  sees. CT_RECON_BURT_ADELSON (1): x = d + upsampled c, the
+ *                  original pyramid's reconstruction, a variant. Both invert
+ *                  the forward transform exactly; they differ on quantised
+ *                  coefficients. The forward transform ignores `recon`.
+ *   A zero-initialised struct with height, width, levels and dirs set is the
+ *   paper's transform. Other values of filters or recon are CT_ERR_GEOM.
  */
 typedef struct ct_geom {
     int32_t height, width;
     int32_t levels;
     int32_t dirs[CT_MAX_LEVELS];
+    int32_t filters;
+    int32_t recon;
 } ct_geom;
+
+enum {
+    CT_FILTERS_CDF97 = 0,
+    CT_FILTERS_LEGALL53 = 1,
+    CT_RECON_DUAL = 0,
+    CT_RECON_BURT_ADELSON = 1
+};
 
 /*
  * Derived layout of one plane.
@@ -235,9 +256,11 @@ int ct_inverse_adjoint(const ct_geom* geom, int32_t batch, const float* gplanes,
  * all streams, run by one launch that covers all their tiles. The groups
  * follow in chain order on one stream. With CT_PLAN_GRAPH the group launches
  * are captured into one HIP graph. With CT_PLAN_AUTOTUNE it times, per LP
- * level shape, whether the deeper DFB tree levels stream one, two or three
- * at a time and caches the choice in a JSON file (CT_AUTOTUNE_CACHE,
- * default $HOME/.cache/ct_autotune.json); every choice gives identical bits.
+ * level shape with three or more DFB tree levels, whether the deeper tree
+ * levels stream one, two or three at a time, and with which row-block height
+ * (the default, half of it or twice it), and caches the choice in a JSON file
+ * (CT_AUTOTUNE_CACHE, default $HOME/.cache/ct_autotune.json); every choice
+ * gives identical bits.
  * ct_plan_run enqueues one graph launch (or the group launches) on `stream`.
  * ct_plan_run_plain enqueues the same work as separate per-stream,
  * per-stage launches (the unbatched baseline); both give identical results.
@@ -265,6 +288,8 @@ typedef struct ct_plan_info_t {
     int32_t levels_paired, levels_single;   /* LP levels with l >= 4 whose deeper tree levels run */
     int32_t levels_triple;                  /* two, one or three per pass (the tuned choice)   */
     int64_t workspace_bytes;
+    int32_t levels_short_blocks;            /* LP levels whose split passes run half-height or   */
+    int32_t levels_tall_blocks;             /* double-height row blocks (the tuned choice)       */
 } ct_plan_info_t;
 
 #define CT_PLAN_GRAPH 1

@@ -68,5 +68,8 @@ def rd_loss(c, x, steps, plan, lam):
     return ((rec - x) ** 2).sum() + lam * c.abs().sum()
 
 
-def make_plan(height, width, levels, dirs, batch, device="cuda"):
-    return _ct.Plan(height, width, levels, dirs, batch, device)
+def make_plan(height, width, levels, dirs, batch, device="cuda", filters="97", recon="dual"):
+    """Plan for the functions above; filters and recon select the variants
+    (see ct.geom): the adjoints follow the plan's filter pair and
+    reconstruction."""
+    return _ct.Plan(height, width, levels, dirs, batch, device, filters=filters, recon=recon)

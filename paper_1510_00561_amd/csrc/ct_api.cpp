@@ -31,23 +31,23 @@ namespace {
 
 enum class Mode { Forward, Inverse, ForwardAdjoint, InverseAdjoint };
 
-Taps5 taps_h() {
-    const Constants& k = constants();
+Taps5 taps_h(int filters) {
+    const Constants& k = constants(filters);
     Taps5 t;
     for (int i = 0; i < 5; ++i) t.t[i] = float(k.hbar[i]);
     return t;
 }
 
-Taps5 taps_g() {
-    const Constants& k = constants();
+Taps5 taps_g(int filters) {
+    const Constants& k = constants(filters);
     Taps5 t;
     for (int i = 0; i < 4; ++i) t.t[i] = float(k.gbar[i]);
     t.t[4] = 0.f;
     return t;
 }
 
-Lift lift_for(Mode m) {
-    const Constants& k = constants();
+Lift lift_for(Mode m, int filters) {
+    const Constants& k = constants(filters);
     Lift L;
     switch (m) {
         case Mode::Forward:   // odd += a N(even); even += b; odd += g; even += d
@@ -68,10 +68,10 @@ Lift lift_for(Mode m) {
 }
 
 // zeta^(sign * e_k) for the final subbands of a DFB with l tree levels
-void scale_table(int l, int sign, float* out) {
+void scale_table(int l, int sign, int filters, float* out) {
     int e[kMaxDirs];
     dfb_scale_exponents(l, e);
-    const double z = constants().zeta;
+    const double z = constants(filters).zeta;
     for (int k = 0; k < (1 << l); ++k) out[k] = float(pow(z, double(sign * e[k])));
 }
 
@@ -183,13 +183,16 @@ int level_block_rows(int Rj, int Cj, int batch, bool synthesis) {
     return block_rows(Rj, strips * batch, resident_waves(), 32, level_max_rows(), 8);
 }
 
-int split_block_rows(const SplitArgs& a, int batch, int levels) {
+int split_block_rows(const SplitArgs& a, int batch, int levels, int height) {
     const int t = a.t, vw = stream_cols(levels);
     const int nrh = a.Rj >> (t - 2), nch = a.Cj >> 1, nrv = a.Cj >> (t - 2), ncv = a.Rj >> 1;
     const int cols = (1 << (t - 2)) * ((nch + vw - 1) / vw + (ncv + vw - 1) / vw) * batch;
     // one-level passes carry a small halo and few instructions per row: they
-    // run fastest with shorter blocks and four times as many wavefronts
-    const int slots = levels == 1 ? 4 * resident_waves() : resident_waves();
+    // run fastest with shorter blocks and four times as many wavefronts. The
+    // tuner's height choice doubles or halves the wavefronts aimed at.
+    int slots = levels == 1 ? 4 * resident_waves() : resident_waves();
+    if (height == kHeightShort) slots *= 2;
+    if (height == kHeightTall) slots /= 2;
     return block_rows(nrh > nrv ? nrh : nrv, cols, slots, 32, stream_max_rows(levels),
                       stream_row_align(levels));
 }
@@ -212,21 +215,28 @@ static int first_subband(const Geometry& g, int j) {
     return s;
 }
 
-// Stage chain of one transform direction (see ct_batched.h). `grouping[j]`
-// selects pairs (2) or single DFB tree levels (1) at LP level j. With `fq`
+// Stage chain of one transform direction (see ct_batched.h). `tune[j]`
+// selects the DFB tree levels per split pass (1, 2 or 3) and the row-block
+// height of the split passes at LP level j (tune_grouping, tune_height). With `fq`
 // the final subbands are quantised where the forward transform produces
 // them, or dequantised where the inverse consumes them (the fused encoder
 // and decoder); the float coefficients `out` / `in` may then be null.
 void build_transform_chain(const Geometry& g, int batch, int mode_i, const float* in, float* out,
-                           char* ws, const Workspace& w, const int* grouping,
+                           char* ws, const Workspace& w, const int* tune,
                            std::vector<StageDesc>& chain, const FusedQuant* fq) {
     const Mode mode = Mode(mode_i);
     const bool analysis = mode == Mode::Forward || mode == Mode::InverseAdjoint;
     const bool plain_filters = mode == Mode::Forward || mode == Mode::Inverse;
-    const Taps5 lo = plain_filters ? taps_h() : taps_g();
-    const Taps5 up = plain_filters ? taps_g() : taps_h();
+    const Taps5 lo = plain_filters ? taps_h(g.filters) : taps_g(g.filters);
+    const Taps5 up = plain_filters ? taps_g(g.filters) : taps_h(g.filters);
     const int lo_r = plain_filters ? 4 : 3;
-    const Lift L = lift_for(mode);
+    const Lift L = lift_for(mode, g.filters);
+    // Burt-Adelson reconstruction: the inverse's LP synthesis without the
+    // correction of c, i.e. the dual-frame stage with a zero correction
+    // filter (its `lo`); the transpose of that synthesis is the LP analysis
+    // without the prediction, i.e. a zero `up`. Zero taps add exact zeros.
+    const bool ba = g.recon == CT_RECON_BURT_ADELSON;
+    const Taps5 zero{};
     const int64_t RC = int64_t(g.R) * g.C;
     float* D = reinterpret_cast<float*>(ws + w.d_off);
     float* A = reinterpret_cast<float*>(ws + w.a_off);
@@ -271,7 +281,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                                              first_subband(g, j)}
                                    : QuantIO{nullptr, 0, nullptr, 0, 0};
             float sc[kMaxDirs];
-            scale_table(l, mode == Mode::Forward ? +1 : -1, sc);
+            scale_table(l, mode == Mode::Forward ? +1 : -1, g.filters, sc);
             for (int k = 0; k < 4; ++k) {
                 a.out.p[k] = l == 2 ? (level ? level + k * q4 : nullptr) : A + k * q4;
                 a.out.scale[k] = l == 2 ? sc[k] : 1.f;
@@ -282,7 +292,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                 d.type = kStLevelAnaQ;
             }
             a.lo = lo;
-            a.up = up;
+            a.up = (ba && mode == Mode::InverseAdjoint) ? zero : up;
             a.L = L;
             a.batch = batch;
             a.bh = level_block_rows(Rj, Cj, batch, false);
@@ -299,7 +309,8 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                              (l == 2 ? chan * double(Rj) * Cj : 0.0));
             push(d);
             int first[4], count[4];
-            const int ng = split_groups(l, grouping[j - 1], first, count);
+            const int ng = split_groups(l, tune_grouping(tune[j - 1]), first, count);
+            const int hm = tune_height(tune[j - 1]);
             float* cur = A;
             float* other = Bf;
             for (int gi = 0; gi < ng; ++gi) {
@@ -325,7 +336,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     sa.child = other;
                     sa.child_plane = RC;
                 }
-                sa.bh = split_block_rows(sa, batch, count[gi]);
+                sa.bh = split_block_rows(sa, batch, count[gi], hm);
                 e.ntiles = split_stage_tiles(sa, batch, count[gi]);
                 const double out_b = last ? (level ? 4.0 : 0.0) + (qio.idx ? 2.0 : 0.0) : 4.0;
                 e.bytes = batch * (4.0 + out_b) * double(Rj) * Cj;
@@ -348,7 +359,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                                          fq->steps_stride, first_subband(g, j)}
                                : QuantIO{nullptr, 0, nullptr, 0, 0};
         float sc[kMaxDirs];
-        scale_table(l, mode == Mode::Inverse ? -1 : +1, sc);
+        scale_table(l, mode == Mode::Inverse ? -1 : +1, g.filters, sc);
         StageDesc d;
         memset(&d, 0, sizeof(d));
         d.type = kStLevelSyn;
@@ -363,7 +374,8 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
             if (qio.idx) d.type = kStLevelSynQ;
         } else {
             int first[4], count[4];
-            const int ng = split_groups(l, grouping[j - 1], first, count);
+            const int ng = split_groups(l, tune_grouping(tune[j - 1]), first, count);
+            const int hm = tune_height(tune[j - 1]);
             float* cur = A;
             float* other = Bf;
             for (int gi = ng - 1; gi >= 0; --gi) {
@@ -388,7 +400,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     sa.parent = other;
                     sa.parent_plane = RC;
                 }
-                sa.bh = split_block_rows(sa, batch, count[gi]);
+                sa.bh = split_block_rows(sa, batch, count[gi], hm);
                 e.ntiles = split_stage_tiles(sa, batch, count[gi]);
                 const double in_b = (gi == ng - 1 && qio.idx) ? 2.0 : 4.0;
                 e.bytes = batch * (in_b + 4.0) * double(Rj) * Cj;
@@ -426,7 +438,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
         } else {
             a.x_out = View{reinterpret_cast<float*>(ws + w.c_off[j - 1]), int64_t(Rj) * Cj, Cj};
         }
-        a.lo = lo;
+        a.lo = (ba && mode == Mode::Inverse) ? zero : lo;
         a.up = up;
         a.L = L;
         a.batch = batch;
@@ -531,7 +543,7 @@ int transform(const ct_geom* geom, int32_t batch, const float* in, float* out, v
     if (!in || !out || !ws) return CT_ERR_ARG;
     const Workspace w = workspace_layout(g, batch);
     if (ws_bytes < w.total) return CT_ERR_WORKSPACE;
-    if (!constants().ok) return CT_ERR_UNSUPPORTED;
+    if (!constants(g.filters).ok) return CT_ERR_UNSUPPORTED;
     if (fault_injected()) return CT_ERR_HIP;
     std::vector<StageDesc> chain;
     build_transform_chain(g, batch, int(mode), in, out, static_cast<char*>(ws), w,
@@ -794,7 +806,7 @@ int ct_encode(const ct_geom* geom, int32_t batch, const float* planes, const flo
     if (steps_stride < 0 || (steps_stride > 0 && steps_stride < g.nsub)) return CT_ERR_ARG;
     const Workspace w = workspace_layout(g, batch);
     if (ws_bytes < w.total) return CT_ERR_WORKSPACE;
-    if (!constants().ok) return CT_ERR_UNSUPPORTED;
+    if (!constants(g.filters).ok) return CT_ERR_UNSUPPORTED;
     if (fault_injected()) return CT_ERR_HIP;
     char* wsc = static_cast<char*>(ws);
     const FusedQuant fq{idx, steps, steps_stride, nullptr};
@@ -818,7 +830,7 @@ int ct_decode(const ct_geom* geom, int32_t batch, const int16_t* idx, const floa
     if (steps_stride < 0 || (steps_stride > 0 && steps_stride < g.nsub)) return CT_ERR_ARG;
     const Workspace w = workspace_layout(g, batch);
     if (ws_bytes < w.total) return CT_ERR_WORKSPACE;
-    if (!constants().ok) return CT_ERR_UNSUPPORTED;
+    if (!constants(g.filters).ok) return CT_ERR_UNSUPPORTED;
     if (fault_injected()) return CT_ERR_HIP;
     const FusedQuant fq{const_cast<int16_t*>(idx), steps, steps_stride, side};
     std::vector<StageDesc> chain;

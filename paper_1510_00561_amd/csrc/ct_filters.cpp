@@ -1,4 +1,5 @@
-// Filters and lifting constants of the 9-7 pair (host only, double precision).
+// Filters and lifting constants of the 9-7 pair and of the LeGall 5/3 variant
+// (host only, double precision).
 //
 // Paper section 2.1: LP and DFB use the Cohen-Daubechies 9-7 biorthogonal
 // filters. Construction used here:
@@ -15,6 +16,12 @@
 // refined here by Newton's method from their published 10-digit values until
 // the lifted analysis lowpass reproduces the closed-form taps to rounding,
 // and the lifted highpass is then checked against q(-t).
+//
+// Variant: the LeGall 5/3 pair, the same construction with two zeros at
+// w = pi on each side: Q(y) = 1 + 2y goes whole to the analysis side,
+//     p(t) ~ ((1+t)/2)(1 + (1-t))    (5 taps),   q(t) ~ (1+t)/2   (3 taps).
+// Its lifting is two steps, predict -1/2 and update 1/4, with the scaling
+// sqrt 2; the same two checks confirm them.
 #include <math.h>
 #include <string.h>
 
@@ -127,7 +134,57 @@ bool solve5(double A[5][5], double* b) {
     return true;
 }
 
-Constants build() {
+// Lowpass taps reproduced by the lifting th, and odd outputs equal to
+// (-1)^n g[n] (the highpass q(-t)).
+bool lifting_matches(const double* th, const double* h, const double* g) {
+    double hl[5];
+    lifted_lowpass(th, hl);
+    bool ok = true;
+    for (int i = 0; i < 5; ++i) ok = ok && fabs(hl[i] - h[i]) < 1e-12;
+    const int N = 32;
+    double x[N];
+    for (int src = 0; src < 2; ++src) {
+        memset(x, 0, sizeof(x));
+        x[src] = 1;
+        lift1d(x, N, th);
+        for (int o = 1; o < N; o += 2) {
+            int n = o - src;       // output at o sees tap gm[o - src]
+            if (n > N / 2) n -= N;
+            int an = n < 0 ? -n : n;
+            double want = an <= 3 ? ((an % 2) ? -g[an] : g[an]) : 0.0;
+            ok = ok && fabs(x[o] - want) < 1e-12;
+        }
+    }
+    return ok;
+}
+
+Constants build53() {
+    Constants k;
+    memset(&k, 0, sizeof(k));
+    Poly half_plus{{0.5, 0.5}, 2};
+    Poly rem{{2.0, -1.0}, 2};              // 1 + 2y with y = (1 - t)/2
+    Poly p = pmul(half_plus, rem);
+    Poly q = half_plus;
+    const double s2 = sqrt(2.0);
+    const double np = s2 / peval(p, 1.0), nq = s2 / peval(q, 1.0);
+    for (int i = 0; i < p.n; ++i) p.c[i] *= np;
+    for (int i = 0; i < q.n; ++i) q.c[i] *= nq;
+    double h[5] = {0, 0, 0, 0, 0}, g[4] = {0, 0, 0, 0};
+    chebyshev_taps(p, h);
+    chebyshev_taps(q, g);
+    for (int i = 0; i < 5; ++i) k.hbar[i] = h[i] / s2;
+    for (int i = 0; i < 4; ++i) k.gbar[i] = g[i] * s2;
+    const double th[5] = {-0.5, 0.25, 0.0, 0.0, s2};
+    k.alpha = th[0];
+    k.beta = th[1];
+    k.gamma = th[2];
+    k.delta = th[3];
+    k.zeta = th[4];
+    k.ok = lifting_matches(th, h, g);
+    return k;
+}
+
+Constants build97() {
     Constants k;
     memset(&k, 0, sizeof(k));
     // real root of 20y^3 + 10y^2 + 4y + 1 by Newton from -0.34
@@ -194,39 +251,20 @@ Constants build() {
     k.gamma = th[2];
     k.delta = th[3];
     k.zeta = th[4];
-    // check: lowpass reproduced, and the odd outputs are q(-t), i.e. taps
-    // (-1)^n g[n] centred on the odd sample
-    double hl[5];
-    lifted_lowpass(th, hl);
-    bool ok = true;
-    for (int i = 0; i < 5; ++i) ok = ok && fabs(hl[i] - h[i]) < 1e-12;
-    {
-        const int N = 32;
-        double x[N];
-        for (int src = 0; src < 2; ++src) {
-            memset(x, 0, sizeof(x));
-            x[src] = 1;
-            lift1d(x, N, th);
-            for (int o = 1; o < N; o += 2) {
-                int n = o - src;       // output at o sees tap gm[o - src]
-                if (n > N / 2) n -= N;
-                int an = n < 0 ? -n : n;
-                double want = an <= 3 ? ((an % 2) ? -g[an] : g[an]) : 0.0;
-                ok = ok && fabs(x[o] - want) < 1e-12;
-            }
-        }
-    }
-    k.ok = ok;
+    k.ok = lifting_matches(th, h, g);
     return k;
 }
 
 }  // namespace
 
-const Constants& constants() {
-    static Constants k;
+const Constants& constants(int filters) {
+    static Constants k[2];
     static std::once_flag once;
-    std::call_once(once, [] { k = build(); });
-    return k;
+    std::call_once(once, [] {
+        k[CT_FILTERS_CDF97] = build97();
+        k[CT_FILTERS_LEGALL53] = build53();
+    });
+    return k[filters == CT_FILTERS_LEGALL53 ? CT_FILTERS_LEGALL53 : CT_FILTERS_CDF97];
 }
 
 }  // namespace ct

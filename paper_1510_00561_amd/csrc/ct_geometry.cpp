@@ -69,6 +69,10 @@ int resolve(const ct_geom* g, Geometry* out) {
     r.H = g->height;
     r.W = g->width;
     r.J = g->levels;
+    if (g->filters != CT_FILTERS_CDF97 && g->filters != CT_FILTERS_LEGALL53) return CT_ERR_GEOM;
+    if (g->recon != CT_RECON_DUAL && g->recon != CT_RECON_BURT_ADELSON) return CT_ERR_GEOM;
+    r.filters = g->filters;
+    r.recon = g->recon;
     r.e = r.J;
     for (int j = 0; j < r.J; ++j) {
         int lj = ilog2_pow2(g->dirs[j]);

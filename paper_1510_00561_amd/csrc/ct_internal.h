@@ -15,6 +15,8 @@ constexpr int kMaxLevels = CT_MAX_LEVELS;
 // Resolved geometry of one plane (host side).
 struct Geometry {
     int H = 0, W = 0, J = 0;
+    int filters = CT_FILTERS_CDF97;  // filter pair of the LP and the DFB
+    int recon = CT_RECON_DUAL;       // LP reconstruction of the inverse
     int dirs[kMaxLevels] = {0};
     int l[kMaxLevels] = {0};         // log2 dirs
     int e = 0;                       // padding exponent
@@ -61,14 +63,16 @@ int quantize_with_partials(const ct_geom* geom, int32_t batch, const float* coef
                            const float* steps, int32_t steps_stride, int16_t* idx, float* side,
                            void* partials, size_t partial_bytes, hipStream_t stream);
 
-// Filters and lifting constants, derived at first use from the closed-form
-// 9-7 pair.
+// Filters and lifting constants, derived at first use from the closed form
+// of a filter pair: CT_FILTERS_CDF97 (the paper's 9-7 pair) or
+// CT_FILTERS_LEGALL53. Shorter filters leave their outer taps and lifting
+// steps zero, so that every stage runs the 9-7 stencils unchanged.
 struct Constants {
     double hbar[5];   // LP analysis lowpass, unit DC: taps 0..4 (symmetric)
     double gbar[4];   // LP synthesis lowpass, sum 2: taps 0..3 (symmetric)
-    double alpha, beta, gamma, delta, zeta;   // 9-7 lifting factorisation
+    double alpha, beta, gamma, delta, zeta;   // lifting factorisation
     bool ok;
 };
-const Constants& constants();
+const Constants& constants(int filters = CT_FILTERS_CDF97);
 
 }  // namespace ct

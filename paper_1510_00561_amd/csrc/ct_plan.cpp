@@ -8,12 +8,13 @@
 // position over all streams; its launch covers all their tiles.
 //
 // Autotuning (CT_PLAN_AUTOTUNE) picks, for every distinct LP level shape
-// with four or more DFB tree levels, how many of the deeper tree levels run
-// per streaming pass (one, two or three: halo 4, 12 or 28 rows), by timing
-// every grouping with HIP events. All groupings compute the same float32
-// operations in the same order, so the choice never changes a result. Choices are cached in a JSON file keyed by device
-// architecture and shape (CT_AUTOTUNE_CACHE, default
-// $HOME/.cache/ct_autotune.json).
+// with three or more DFB tree levels, how many of the deeper tree levels run
+// per streaming pass (one, two or three: halo 4, 12 or 28 rows) and the
+// row-block height of those passes (the host's default, about half of it or
+// about twice it), by timing every combination with HIP events. All choices
+// compute the same float32 operations in the same order, so none changes a
+// result. Choices are cached in a JSON file keyed by device architecture and
+// shape (CT_AUTOTUNE_CACHE, default $HOME/.cache/ct_autotune.json).
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -39,7 +40,7 @@ struct ct_plan {
     std::vector<size_t> ws_off;
     char* ws = nullptr;
     std::vector<std::vector<StageDesc>> chains;     // per stream, chain order
-    std::vector<int> grouping;                      // [stream * kMaxLevels + j]
+    std::vector<int> grouping;                      // tune codes [stream * kMaxLevels + j]
     struct Group {
         int type, stage0, n, tiles;    // stages [stage0, stage0 + n) of d_stages / d_first
     };
@@ -109,8 +110,9 @@ std::string arch_name(int dev) {
 }
 
 // Time the DFB split passes (analysis then synthesis) of one LP level shape
-// with the given grouping, using workspace buffers as scratch.
-float time_level_splits(int Rj, int Cj, int l, int batch, int grouping, float* A, float* B,
+// with the given grouping and block height, using workspace buffers as
+// scratch.
+float time_level_splits(int Rj, int Cj, int l, int batch, int grouping, int height, float* A, float* B,
                         float* D, int64_t plane, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     int first[4], count[4], ng = 0;
     for (int t = 3; t <= l;) {
@@ -139,7 +141,7 @@ float time_level_splits(int Rj, int Cj, int l, int batch, int grouping, float* A
             a.child = gi == ng - 1 ? D : other;
             a.child_plane = plane;
             a.plane_elems = int64_t(Rj) * Cj;
-            a.bh = split_block_rows(a, batch, count[gi]);
+            a.bh = split_block_rows(a, batch, count[gi], height);
             hipError_t e = ana[count[gi] - 1](a, L, batch, st);
             if (e != hipSuccess) return false;
             std::swap(cur, other);
@@ -157,7 +159,7 @@ float time_level_splits(int Rj, int Cj, int l, int batch, int grouping, float* A
             a.child = cur2;
             a.child_plane = plane;
             a.plane_elems = int64_t(Rj) * Cj;
-            a.bh = split_block_rows(a, batch, count[gi]);
+            a.bh = split_block_rows(a, batch, count[gi], height);
             hipError_t e = syn[count[gi] - 1](a, L, batch, st);
             if (e != hipSuccess) return false;
             std::swap(cur2, other2);
@@ -173,6 +175,12 @@ float time_level_splits(int Rj, int Cj, int l, int batch, int grouping, float* A
     float ms = 0;
     if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
     return ms;
+}
+
+// A cached code the chain builder can use (anything else is tuned again).
+bool valid_tune(int code) {
+    const int g = tune_grouping(code), h = tune_height(code);
+    return code >= 0 && (code >> 6) == 0 && g >= 1 && g <= 3 && h <= kHeightTall;
 }
 
 int autotune(ct_plan* p, hipStream_t st) {
@@ -193,34 +201,35 @@ int autotune(ct_plan* p, hipStream_t st) {
         const Workspace& w = p->wls[s];
         for (int j = 1; j <= g.J; ++j) {
             const int l = g.l[j - 1];
-            if (l < 4) continue;    // one grouping only
+            if (l < 3) continue;    // no split pass
             const int Rj = g.R >> (j - 1), Cj = g.C >> (j - 1);
             char key[160];
-            snprintf(key, sizeof(key), "%s|split_grouping|%dx%d|l%d|b%d", arch.c_str(), Rj, Cj, l, batch);
+            snprintf(key, sizeof(key), "%s|split_tune|%dx%d|l%d|b%d", arch.c_str(), Rj, Cj, l, batch);
             auto it = cache.find(key);
             int choice;
-            if (it != cache.end()) {
+            if (it != cache.end() && valid_tune(it->second)) {
                 choice = it->second;
             } else {
                 float* A = reinterpret_cast<float*>(ws + w.a_off);
                 float* B = reinterpret_cast<float*>(ws + w.b_off);
                 float* D = reinterpret_cast<float*>(ws + w.d_off);
                 const int64_t plane = int64_t(g.R) * g.C;
-                // every grouping that differs for this depth: up to l - 2
-                // levels per pass
+                // every grouping that differs for this depth (up to l - 2
+                // levels per pass), at each of the three block heights
                 float best = -1.f;
-                choice = 1;
-                for (int grp = 1; grp <= 3 && grp <= l - 2; ++grp) {
-                    const float ms = time_level_splits(Rj, Cj, l, batch, grp, A, B, D, plane, st, e0, e1);
-                    if (ms < 0) {
-                        rc = CT_ERR_HIP;
-                        break;
+                choice = tune_code(1, kHeightDefault);
+                for (int grp = 1; grp <= 3 && grp <= l - 2 && rc == CT_OK; ++grp)
+                    for (int hm = kHeightDefault; hm <= kHeightTall; ++hm) {
+                        const float ms = time_level_splits(Rj, Cj, l, batch, grp, hm, A, B, D, plane, st, e0, e1);
+                        if (ms < 0) {
+                            rc = CT_ERR_HIP;
+                            break;
+                        }
+                        if (best < 0 || ms < best) {
+                            best = ms;
+                            choice = tune_code(grp, hm);
+                        }
                     }
-                    if (best < 0 || ms < best) {
-                        best = ms;
-                        choice = grp;
-                    }
-                }
                 if (rc != CT_OK) break;
                 cache[key] = choice;
                 dirty = true;
@@ -274,7 +283,7 @@ int ct_plan_create(const ct_stream_desc* streams, int32_t n, int32_t flags, ct_p
     if (!out) return CT_ERR_ARG;
     *out = nullptr;
     if (!streams || n < 1 || n > 4096) return CT_ERR_ARG;
-    if (!constants().ok) return CT_ERR_UNSUPPORTED;
+    if (!constants(CT_FILTERS_CDF97).ok || !constants(CT_FILTERS_LEGALL53).ok) return CT_ERR_UNSUPPORTED;
     ct_plan* p = new ct_plan();
     p->streams.assign(streams, streams + n);
     p->geoms.resize(n);
@@ -426,17 +435,21 @@ int ct_plan_info(const ct_plan* p, ct_plan_info_t* info) {
     info->launches = int32_t(p->groups.size());
     info->graph = p->exec ? 1 : 0;
     info->autotuned = p->autotuned;
-    int n[4] = {0, 0, 0, 0};
+    int n[4] = {0, 0, 0, 0}, h[3] = {0, 0, 0};
     for (size_t s = 0; s < p->streams.size(); ++s)
         for (int j = 0; j < p->geoms[s].J; ++j) {
             const int l = p->geoms[s].l[j];
-            int grp = p->grouping[s * kMaxLevels + j];
+            const int code = p->grouping[s * kMaxLevels + j];
+            int grp = tune_grouping(code);
             if (grp > l - 2) grp = l - 2;       // the same passes as l - 2 levels per pass
             if (l >= 4) n[grp]++;
+            if (l >= 3) h[tune_height(code)]++;
         }
     info->levels_single = n[1];
     info->levels_paired = n[2];
     info->levels_triple = n[3];
+    info->levels_short_blocks = h[kHeightShort];
+    info->levels_tall_blocks = h[kHeightTall];
     info->workspace_bytes = 0;
     for (size_t s = 0; s < p->streams.size(); ++s) info->workspace_bytes += p->wls[s].total;
     return CT_OK;

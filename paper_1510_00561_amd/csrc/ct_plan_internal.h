@@ -41,8 +41,16 @@ struct FusedQuant {
     int steps_stride;
     const float* side;
 };
+// Per-LP-level tuning of the split passes, one int per level: the DFB tree
+// levels per pass (bits 0-3: 1, 2 or 3) and the row-block height (bits 4-5:
+// kHeightDefault, kHeightShort = about half the rows, kHeightTall = about
+// twice). Every code computes the same operations in the same order.
+enum { kHeightDefault = 0, kHeightShort = 1, kHeightTall = 2 };
+inline int tune_grouping(int code) { return code & 15; }
+inline int tune_height(int code) { return (code >> 4) & 3; }
+inline int tune_code(int grouping, int height) { return grouping | (height << 4); }
 void build_transform_chain(const Geometry& g, int batch, int mode, const float* in, float* out,
-                           char* ws, const Workspace& w, const int* grouping,
+                           char* ws, const Workspace& w, const int* tune,
                            std::vector<StageDesc>& chain, const FusedQuant* fq = nullptr);
 // Quantiser stages of the lowpass alone (fused encoder): `low` holds each
 // plane's lowpass at stride `low_plane`.
@@ -61,7 +69,7 @@ int fill_quant_args(const Geometry& g, QuantArgs* a);
 int resident_waves();
 // Rows per streamed block of an LP-level stage and of a split stage.
 int level_block_rows(int Rj, int Cj, int batch, bool synthesis);
-int split_block_rows(const SplitArgs& a, int batch, int levels);
+int split_block_rows(const SplitArgs& a, int batch, int levels, int height = kHeightDefault);
 
 // Work-queue tiles of an LP-level stage (one wavefront item per strip and
 // row block, kBatchedThreads / 64 per tile).

@@ -25,7 +25,13 @@ ERRORS = {0: "CT_OK", -1: "CT_ERR_ARG", -2: "CT_ERR_GEOM", -3: "CT_ERR_WORKSPACE
 
 class Geom(ctypes.Structure):
     _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32),
-                ("levels", ctypes.c_int32), ("dirs", ctypes.c_int32 * MAX_LEVELS)]
+                ("levels", ctypes.c_int32), ("dirs", ctypes.c_int32 * MAX_LEVELS),
+                ("filters", ctypes.c_int32), ("recon", ctypes.c_int32)]
+
+
+# filter pair and LP reconstruction of a geometry (ct_geom.filters / .recon)
+FILTERS = {"97": 0, "53": 1}
+RECON = {"dual": 0, "ba": 1}
 
 
 class Layout(ctypes.Structure):
@@ -62,7 +68,8 @@ class PlanInfo(ctypes.Structure):
                 ("work_items", ctypes.c_int32), ("launches", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("autotuned", ctypes.c_int32),
                 ("levels_paired", ctypes.c_int32), ("levels_single", ctypes.c_int32),
-                ("levels_triple", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
+                ("levels_triple", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
+                ("levels_short_blocks", ctypes.c_int32), ("levels_tall_blocks", ctypes.c_int32)]
 
 
 PLAN_GRAPH = 1
@@ -135,9 +142,13 @@ def _lib():
     return _LIB
 
 
-def geom(height, width, levels, dirs):
+def geom(height, width, levels, dirs, filters="97", recon="dual"):
+    """ct_geom; filters "97" (the 9-7 pair) or "53" (LeGall 5/3), recon "dual"
+    (dual-frame LP synthesis) or "ba" (Burt-Adelson); the codes 0 / 1 work too."""
     d = list(dirs) + [0] * (MAX_LEVELS - len(dirs))
-    return Geom(int(height), int(width), int(levels), (ctypes.c_int32 * MAX_LEVELS)(*d))
+    f = FILTERS.get(filters, filters)
+    r = RECON.get(recon, recon)
+    return Geom(int(height), int(width), int(levels), (ctypes.c_int32 * MAX_LEVELS)(*d), int(f), int(r))
 
 
 def _check(name, rc):
@@ -185,11 +196,11 @@ def workspace_bytes(height, width, levels, dirs, batch):
 class Plan:
     """Geometry + reusable workspace for one batch size on one device."""
 
-    def __init__(self, height, width, levels, dirs, batch, device="cuda"):
+    def __init__(self, height, width, levels, dirs, batch, device="cuda", filters="97", recon="dual"):
         self.height, self.width, self.levels = int(height), int(width), int(levels)
         self.dirs = [int(d) for d in dirs]
         self.batch = int(batch)
-        self.g = geom(height, width, levels, dirs)
+        self.g = geom(height, width, levels, dirs, filters, recon)
         self.layout, self.table = layout(height, width, levels, dirs)
         self.ncoef = int(self.layout.ncoef)
         self.nsub = int(self.layout.nsub)
@@ -527,7 +538,7 @@ class Batched:
 
     streams: list of dicts with keys height, width, levels, dirs, planes
     ([batch, H, W] float32 CUDA tensor) and steps ([nsub] or [batch, nsub]
-    float32 CUDA tensor). Output buffers are allocated here and exposed per
+    float32 CUDA tensor), and optionally filters and recon (see geom). Output buffers are allocated here and exposed per
     stream as coeffs, idx, side, deq, out. With fused=True the plan runs the
     fused encoder and decoder: coeffs and deq are None (not written).
     """
@@ -554,7 +565,7 @@ class Batched:
                        out=torch.empty((B, H, W), dtype=torch.float32, device=self.device))
             self.streams.append(rec)
             d = descs[i]
-            d.geom = geom(H, W, J, dirs)
+            d.geom = geom(H, W, J, dirs, st.get("filters", "97"), st.get("recon", "dual"))
             d.batch = B
             d.planes = rec["planes"].data_ptr()
             d.coeffs = rec["coeffs"].data_ptr() if rec["coeffs"] is not None else None

@@ -210,3 +210,24 @@ def test_quantize_noalloc_validation(ct):
     assert f(ctypes.byref(g), 1025, d, d, 0, d, d, None) == -3           # beyond the static scratch
     bad = ct.geom(256, 256, 2, [8, 6])
     assert f(ctypes.byref(bad), 1, d, d, 0, d, d, None) == -2
+
+
+def test_variant_fields_validated(ct):
+    """ct_geom.filters and .recon: 0 and 1 are served, anything else is a
+    geometry error; the layout does not depend on them."""
+    lib = ct._lib()
+    n = ctypes.c_size_t(0)
+    base = ct.layout(70, 90, 3, [16, 8, 4])[0]
+    for f, r in ((0, 0), (1, 0), (0, 1), (1, 1)):
+        g = ct.geom(70, 90, 3, [16, 8, 4], f, r)
+        assert lib.ct_workspace_bytes(ctypes.byref(g), 2, ctypes.byref(n)) == 0
+        lay = ct.Layout()
+        assert lib.ct_layout_query(ctypes.byref(g), ctypes.byref(lay), None, 0) == 0
+        assert (lay.pad_h, lay.pad_w, lay.ncoef, lay.nsub) == (base.pad_h, base.pad_w, base.ncoef, base.nsub)
+    assert ct.geom(70, 90, 3, [16, 8, 4], "53", "ba").filters == 1
+    assert ct.geom(70, 90, 3, [16, 8, 4], "53", "ba").recon == 1
+    for f, r in ((2, 0), (-1, 0), (0, 2), (0, -1)):
+        g = ct.geom(70, 90, 3, [16, 8, 4], f, r)
+        assert lib.ct_workspace_bytes(ctypes.byref(g), 2, ctypes.byref(n)) == -2
+        d = ctypes.c_void_p(0x1000)
+        assert lib.ct_forward(ctypes.byref(g), 1, d, d, d, 1 << 30, None) == -2

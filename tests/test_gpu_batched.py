@@ -123,9 +123,10 @@ def test_batched_parity_with_oracle():
     plan.close()
 
 
-def _grouping_keys(streams):
-    """Autotune cache keys of every LP level shape with four or more DFB tree
-    levels in `streams` (the levels whose deeper tree levels can be grouped)."""
+def _tune_keys(streams):
+    """(autotune cache key, l) of every LP level with three or more DFB tree
+    levels in `streams` (the levels that run split passes), one entry per
+    stream and level."""
     from paper_1510_00561_amd import ct
     arch = torch.cuda.get_device_properties(0).gcnArchName
     keys = []
@@ -133,9 +134,13 @@ def _grouping_keys(streams):
         lay = ct.layout(H, W, J, dirs)[0]
         for j in range(1, J + 1):
             l = int(np.log2(dirs[j - 1]))
-            if l >= 4:
-                keys.append(f"{arch}|split_grouping|{lay.pad_h >> (j - 1)}x{lay.pad_w >> (j - 1)}|l{l}|b{B}")
+            if l >= 3:
+                keys.append((f"{arch}|split_tune|{lay.pad_h >> (j - 1)}x{lay.pad_w >> (j - 1)}|l{l}|b{B}", l))
     return keys
+
+
+def _valid_code(v):
+    return 1 <= (v & 15) <= 3 and (v >> 4) in (0, 1, 2)
 
 
 def test_autotuned_plan(tmp_path, monkeypatch):
@@ -145,11 +150,11 @@ def test_autotuned_plan(tmp_path, monkeypatch):
     plan = ct.Batched(_streams(3), graph=True, autotune=True)
     info = plan.info()
     assert info["autotuned"] == 1
-    assert info["levels_paired"] + info["levels_single"] > 0
+    assert info["levels_paired"] + info["levels_single"] + info["levels_triple"] > 0
     assert cache.exists()
     entries = json.loads(cache.read_text())
-    assert entries and all(v in (1, 2, 3) for v in entries.values())
-    assert set(_grouping_keys(STREAMS)) <= set(entries)
+    assert entries and all(_valid_code(v) for v in entries.values())
+    assert {k for k, _ in _tune_keys(STREAMS)} <= set(entries)
     plan.run()
     torch.cuda.synchronize()
     tuned = _snapshot(plan)
@@ -161,32 +166,38 @@ def test_autotuned_plan(tmp_path, monkeypatch):
     ref.close()
 
 
-def test_split_groupings_are_bit_identical(tmp_path, monkeypatch):
-    """Every tile-shape choice of the autotuner computes the same float32
-    operations in the same order, so the codec's output bits do not depend
-    on the cache: one level per pass and two levels per pass agree exactly."""
+def test_split_tile_shapes_are_bit_identical(tmp_path, monkeypatch):
+    """Every tile-shape choice of the autotuner (tree levels per pass, row-block
+    height) computes the same float32 operations in the same order, so the
+    codec's output bits do not depend on the cache."""
     from paper_1510_00561_amd import ct
-    keys = _grouping_keys(STREAMS)
-    assert keys
+    keys = _tune_keys(STREAMS)
+    deep = [l for _, l in keys if l >= 4]
+    assert deep
     snaps = []
-    for choice in (1, 2, 3):
-        cache = tmp_path / f"forced{choice}.json"
-        cache.write_text(json.dumps({k: choice for k in keys}))
+    # codes: tree levels per pass in bits 0-3, block height in bits 4-5
+    # (0 default, 1 short, 2 tall)
+    for code in (1, 2, 3, 1 | 16, 3 | 16, 2 | 32, 3 | 32):
+        cache = tmp_path / f"forced{code}.json"
+        cache.write_text(json.dumps({k: code for k, _ in keys}))
         monkeypatch.setenv("CT_AUTOTUNE_CACHE", str(cache))
         plan = ct.Batched(_streams(5), graph=True, autotune=True)
         info = plan.info()
-        assert info["levels_single"] + info["levels_paired"] + info["levels_triple"] == len(keys)
-        if choice == 1:
-            assert info["levels_single"] == len(keys)
-        else:
-            assert info["levels_single"] == 0
+        grp, hm = code & 15, code >> 4
+        # a level with l tree levels runs at most l - 2 of them per pass
+        want = {1: 0, 2: 0, 3: 0}
+        for l in deep:
+            want[min(grp, l - 2)] += 1
+        assert (info["levels_single"], info["levels_paired"], info["levels_triple"]) == (want[1], want[2], want[3])
+        assert info["levels_short_blocks"] == (len(keys) if hm == 1 else 0)
+        assert info["levels_tall_blocks"] == (len(keys) if hm == 2 else 0)
         plan.run()
         torch.cuda.synchronize()
         snaps.append(_snapshot(plan))
         plan.close()
-        print(f"[batched] grouping {choice} done", flush=True)
-    _same(snaps[0], snaps[1])
-    _same(snaps[0], snaps[2])
+        print(f"[batched] tune code {code} done", flush=True)
+    for s in snaps[1:]:
+        _same(snaps[0], s)
 
 
 def test_fused_plan_equals_encode_decode():
