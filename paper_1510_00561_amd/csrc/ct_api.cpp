@@ -188,9 +188,12 @@ int split_block_rows(const SplitArgs& a, int batch, int levels, int height) {
     const int nrh = a.Rj >> (t - 2), nch = a.Cj >> 1, nrv = a.Cj >> (t - 2), ncv = a.Rj >> 1;
     const int cols = (1 << (t - 2)) * ((nch + vw - 1) / vw + (ncv + vw - 1) / vw) * batch;
     // one-level passes carry a small halo and few instructions per row: they
-    // run fastest with shorter blocks and four times as many wavefronts. The
-    // tuner's height choice doubles or halves the wavefronts aimed at.
-    int slots = levels == 1 ? 4 * resident_waves() : resident_waves();
+    // run fastest with shorter blocks and four times as many wavefronts;
+    // three-level passes with twice as many (1080p level 1: 120-row instead
+    // of 240-row blocks, 318 against 338 us for the quantising analysis; three
+    // and four times as many were slower). The tuner's height choice doubles
+    // or halves the wavefronts aimed at.
+    int slots = levels == 1 ? 4 * resident_waves() : levels == 3 ? 2 * resident_waves() : resident_waves();
     if (height == kHeightShort) slots *= 2;
     if (height == kHeightTall) slots /= 2;
     return block_rows(nrh > nrv ? nrh : nrv, cols, slots, 32, stream_max_rows(levels),

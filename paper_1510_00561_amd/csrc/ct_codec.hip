@@ -2,27 +2,28 @@
 // (section 3.8) of the quantised CT components, for gfx950.
 //
 // Motion compensation is one pass over the indices, one wavefront per stored
-// row of a component: every element finds the 16 x 16 block of the
-// luminance pixel it sits on, that block's vector mapped to the component's
-// sample spacing (rounded, halves away from zero), and subtracts (or, for
-// the decoder, adds) the previous plane's element at the displaced position,
-// modulo the component's size and modulo 2^16. HBM-bound: 2 bytes read,
-// 2 gathered (mostly within the lines of nearby rows) and 2 written per
-// element.
+// row of a component, four consecutive elements per lane: every element finds
+// the 16 x 16 block of the luminance pixel it sits on, that block's vector
+// mapped to the component's sample spacing (rounded, halves away from zero),
+// and subtracts (or, for the decoder, adds) the previous plane's element at
+// the displaced position, modulo the component's size and modulo 2^16.
+// HBM-bound: 2 bytes read, 2 gathered (mostly within the lines of nearby
+// rows) and 2 written per element.
 //
 // The zero-run coder is a stream compaction in three passes:
 //   1. symbols per natural row: rows stored contiguously (the lowpass, the
 //      horizontal-cone subbands) take one wavefront each, lanes along the
-//      row; rows of the transposed vertical-cone subbands are stored
-//      columns, so one wavefront takes 64 of them, one per lane, and walks
-//      down the stored rows with coalesced loads;
+//      row, four elements per lane; rows of the transposed vertical-cone
+//      subbands are stored columns, so one wavefront takes 64 of them, one
+//      per lane, and walks down the stored rows with coalesced loads;
 //   2. per plane, an exclusive scan of the row counts (one workgroup per
 //      plane) gives every row's symbol offset and every component's offset;
-//   3. symbols: the same decomposition as pass 1. Within a wavefront, a
-//      row's symbol positions come from a prefix sum of the per-element
-//      symbol counts (1 for a non-zero value, 2 for the first zero of a run),
-//      and the element that ends a run writes its length next to the run's
-//      0, found from a prefix maximum of the last non-zero position.
+//   3. symbols: the same decomposition as pass 1. Along a contiguous row,
+//      lanes take four consecutive elements each; a row's symbol positions
+//      come from a prefix sum of the per-element symbol counts (1 for a
+//      non-zero value, 2 for the first zero of a run), and the element that
+//      ends a run writes its length next to the run's 0, found from a prefix
+//      maximum of the last non-zero position.
 #include "ct_codec.h"
 
 namespace ct {
@@ -177,28 +178,61 @@ __global__ __launch_bounds__(NT) void mc_kernel(MCArgs A, MCItems IT) {
     // the fixed coordinate's block and pixel
     const int fixed_px = m.f * ((m.tr ? m.o2 : m.o1) + (m.tr ? m.s2 : m.s1) * m.fixed);
     const int fixed_blk = m.tr ? min(fixed_px >> 4, A.nbx - 1) : min(fixed_px >> 4, A.nby - 1);
-    for (int e = lane; e < m.len; e += 64) {
-        // the varying coordinate: natural column (row-major) or row (transposed)
-        const int px = m.f * ((m.tr ? m.o1 : m.o2) + (m.tr ? m.s1 : m.s2) * e);
-        int by, bx, i, k;
-        if (m.tr) {
-            by = min(px >> 4, A.nby - 1);
-            bx = fixed_blk;
-            i = e;
-            k = m.fixed;
+    // lanes take four consecutive elements each: one 8-byte load and store of
+    // the row when it is 8-byte aligned (the gathers stay per element)
+    const int16_t* crow = cur + m.start;
+    int16_t* orow = out + m.start;
+    const bool vec = ((reinterpret_cast<uintptr_t>(crow) | reinterpret_cast<uintptr_t>(orow)) & 7) == 0;
+    const bool mv4 = (reinterpret_cast<uintptr_t>(mv) & 3) == 0;
+    const int vo = m.tr ? m.o1 : m.o2, vs = m.tr ? m.s1 : m.s2;
+    for (int e0 = 4 * lane; e0 < m.len; e0 += 256) {
+        const bool full = vec && e0 + 4 <= m.len;
+        int cv[4];
+        if (full) {
+            const int2 w = *reinterpret_cast<const int2*>(crow + e0);
+            cv[0] = int16_t(w.x & 0xffff);
+            cv[1] = int16_t(uint32_t(w.x) >> 16);
+            cv[2] = int16_t(w.y & 0xffff);
+            cv[3] = int16_t(uint32_t(w.y) >> 16);
         } else {
-            by = fixed_blk;
-            bx = min(px >> 4, A.nbx - 1);
-            i = m.fixed;
-            k = e;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cv[q] = e0 + q < m.len ? int(crow[e0 + q]) : 0;
         }
-        const int16_t* v = mv + (by * A.nbx + bx) * 2;
-        const int i2 = wrap(i + round_div_fast(v[0], 2 * sy, rby), m.rows);
-        const int k2 = wrap(k + round_div_fast(v[1], 2 * sx, rbx), m.cols);
-        const int64_t src = m.base + (m.tr ? int64_t(k2) * m.rows + i2 : int64_t(i2) * m.cols + k2);
-        const int pv = prev[src];
-        const int cv = cur[m.start + e];
-        out[m.start + e] = int16_t(A.inverse ? cv + pv : cv - pv);   // modulo 2^16
+        int r[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = min(e0 + q, m.len - 1);   // past the row end: a valid element, not stored
+            // the varying coordinate: natural column (row-major) or row (transposed)
+            const int px = m.f * (vo + vs * e);
+            const int vb = m.tr ? min(px >> 4, A.nby - 1) : min(px >> 4, A.nbx - 1);
+            const int by = m.tr ? vb : fixed_blk, bx = m.tr ? fixed_blk : vb;
+            const int16_t* v = mv + (by * A.nbx + bx) * 2;
+            int dy, dx;
+            if (mv4) {
+                const int w = *reinterpret_cast<const int*>(v);
+                dy = int16_t(w & 0xffff);
+                dx = int16_t(uint32_t(w) >> 16);
+            } else {
+                dy = v[0];
+                dx = v[1];
+            }
+            const int i = m.tr ? e : m.fixed, k = m.tr ? m.fixed : e;
+            const int i2 = wrap(i + round_div_fast(dy, 2 * sy, rby), m.rows);
+            const int k2 = wrap(k + round_div_fast(dx, 2 * sx, rbx), m.cols);
+            const int64_t src = m.base + (m.tr ? int64_t(k2) * m.rows + i2 : int64_t(i2) * m.cols + k2);
+            const int pv = prev[src];
+            r[q] = A.inverse ? cv[q] + pv : cv[q] - pv;   // modulo 2^16 on the store
+        }
+        if (full) {
+            int2 w;
+            w.x = int((uint32_t(r[0]) & 0xffffu) | (uint32_t(r[1]) << 16));
+            w.y = int((uint32_t(r[2]) & 0xffffu) | (uint32_t(r[3]) << 16));
+            *reinterpret_cast<int2*>(orow + e0) = w;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (e0 + q < m.len) orow[e0 + q] = int16_t(r[q]);
+        }
     }
 }
 
@@ -285,6 +319,22 @@ struct ItemTable {
     int item0[kMaxLevels + 3];
 };
 
+// Elements e0 .. e0 + 3 of a row of `len` (1 past the end: a non-zero value
+// that ends any run and is never coded); one 8-byte load when the row is
+// 8-byte aligned and the four are inside it.
+__device__ __forceinline__ void load4(const int16_t* x, int e0, int len, bool aligned, int* v) {
+    if (aligned && e0 + 4 <= len) {
+        const int2 w = *reinterpret_cast<const int2*>(x + e0);
+        v[0] = int16_t(w.x & 0xffff);
+        v[1] = int16_t(uint32_t(w.x) >> 16);
+        v[2] = int16_t(w.y & 0xffff);
+        v[3] = int16_t(uint32_t(w.y) >> 16);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = e0 + q < len ? int(x[e0 + q]) : 1;
+    }
+}
+
 __global__ __launch_bounds__(NT) void rle_count_kernel(RLEArgs A, ItemTable IT) {
     const LevelTable& T = A.T;
     const int per = IT.item0[T.J + 1];
@@ -301,15 +351,20 @@ __global__ __launch_bounds__(NT) void rle_count_kernel(RLEArgs A, ItemTable IT) 
         if (!m.coded) {
             c = m.len;
         } else {
+            const bool al = (reinterpret_cast<uintptr_t>(x) & 7) == 0;
             int carry = 1;                         // before the row: "non-zero"
-            for (int c0 = 0; c0 < m.len; c0 += 64) {
-                const int e = c0 + lane;
-                const bool in = e < m.len;
-                const int v = in ? x[e] : 1;
-                const int up = __shfl_up(v, 1, 64);
-                const int pv = lane == 0 ? carry : up;
-                c += in ? (v != 0 ? 1 : (pv != 0 ? 2 : 0)) : 0;
-                carry = __shfl(v, 63, 64);
+            for (int c0 = 0; c0 < m.len; c0 += 256) {
+                const int e0 = c0 + 4 * lane;
+                int v[4];
+                load4(x, e0, m.len, al, v);
+                const int up = __shfl_up(v[3], 1, 64);
+                int pv = lane == 0 ? carry : up;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (e0 + q < m.len) c += v[q] != 0 ? 1 : (pv != 0 ? 2 : 0);
+                    pv = v[q];
+                }
+                carry = __shfl(v[3], 63, 64);
             }
             c = wave_incl_sum(c);
             c = __shfl(c, 63, 64);
@@ -371,6 +426,33 @@ __global__ __launch_bounds__(SCAN_NT) void rle_scan_kernel(RLEArgs A) {
     if (threadIdx.x == 0) so[A.nsub] = tot;
 }
 
+// Zero-run symbols of one natural row of `len` elements at stride `ld`,
+// written from dst[pos] on.
+__device__ __forceinline__ void rle_column(const int16_t* x, int len, int ld, int16_t* dst, int pos) {
+    bool in_run = false;
+    int run_tok = 0, run_len = 0;
+    for (int r = 0; r < len; ++r) {
+        const int v = x[int64_t(r) * ld];
+        if (v != 0) {
+            if (in_run) {
+                dst[run_tok + 1] = int16_t(run_len);
+                in_run = false;
+            }
+            dst[pos++] = int16_t(v);
+        } else {
+            if (!in_run) {
+                in_run = true;
+                run_tok = pos;
+                dst[pos] = 0;
+                pos += 2;
+                run_len = 0;
+            }
+            ++run_len;
+        }
+    }
+    if (in_run) dst[run_tok + 1] = int16_t(run_len);
+}
+
 __global__ __launch_bounds__(NT) void rle_write_kernel(RLEArgs A, ItemTable IT) {
     const LevelTable& T = A.T;
     const int per = IT.item0[T.J + 1];
@@ -389,61 +471,64 @@ __global__ __launch_bounds__(NT) void rle_write_kernel(RLEArgs A, ItemTable IT) 
             for (int e = lane; e < m.len; e += 64) out[pos + e] = x[e];
             return;
         }
-        int carry = 1;            // previous element (before the row: non-zero)
+        const bool al = (reinterpret_cast<uintptr_t>(x) & 7) == 0;
+        int carry = 1;            // element before the chunk (before the row: non-zero)
         int lastnz = -1;          // last non-zero position before the chunk
-        for (int c0 = 0; c0 < m.len; c0 += 64) {
-            const int e = c0 + lane;
-            const bool in = e < m.len;
-            const int v = in ? x[e] : 1;
-            const int up = __shfl_up(v, 1, 64);
-            const int dn = __shfl_down(v, 1, 64);
-            const int pv = lane == 0 ? carry : up;
-            const int nv = lane == 63 ? (e + 1 < m.len ? int(x[e + 1]) : 1) : (e + 1 < m.len ? dn : 1);
-            const int s = in ? (v != 0 ? 1 : (pv != 0 ? 2 : 0)) : 0;
-            const int incl = wave_incl_sum(s);
-            const int p = pos + incl - s;
-            const int nz = max(lastnz, wave_incl_max(in && v != 0 ? e : -1));
-            if (in) {
-                if (v != 0) {
-                    out[p] = int16_t(v);
-                } else {
-                    if (pv != 0) out[p] = 0;                 // a run starts here
-                    if (nv != 0) {                           // and ends here
-                        const int start = nz + 1;
-                        out[start == e ? p + 1 : p - 1] = int16_t(e - start + 1);
+        for (int c0 = 0; c0 < m.len; c0 += 256) {
+            const int e0 = c0 + 4 * lane;
+            int v[4];
+            load4(x, e0, m.len, al, v);
+            const int up = __shfl_up(v[3], 1, 64);
+            const int dn = __shfl_down(v[0], 1, 64);
+            const int pv0 = lane == 0 ? carry : up;
+            // the element after e0 + 3
+            const int nv3 = lane == 63 ? (e0 + 4 < m.len ? int(x[e0 + 4]) : 1) : (e0 + 4 < m.len ? dn : 1);
+            int sc[4], tot = 0, lnz = -1;
+            int pv = pv0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool in = e0 + q < m.len;
+                sc[q] = in ? (v[q] != 0 ? 1 : (pv != 0 ? 2 : 0)) : 0;
+                tot += sc[q];
+                if (in && v[q] != 0) lnz = e0 + q;
+                pv = v[q];
+            }
+            const int incl = wave_incl_sum(tot);
+            const int nzi = wave_incl_max(lnz);
+            const int nzu = __shfl_up(nzi, 1, 64);
+            int nz = max(lastnz, lane == 0 ? -1 : nzu);   // last non-zero before e0
+            int p = pos + incl - tot;
+            pv = pv0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = e0 + q;
+                if (e < m.len) {
+                    const int nv = q < 3 ? v[q + 1] : nv3;
+                    if (v[q] != 0) {
+                        out[p] = int16_t(v[q]);
+                        nz = e;
+                    } else {
+                        if (pv != 0) out[p] = 0;                     // a run starts here
+                        if (nv != 0) {                               // and ends here
+                            const int start = nz + 1;
+                            out[start == e ? p + 1 : p - 1] = int16_t(e - start + 1);
+                        }
                     }
                 }
+                p += sc[q];
+                pv = v[q];
             }
             pos += __shfl(incl, 63, 64);
-            carry = __shfl(v, 63, 64);
-            lastnz = __shfl(nz, 63, 64);
+            carry = __shfl(v[3], 63, 64);
+            lastnz = max(lastnz, __shfl(nzi, 63, 64));
         }
     } else {
+        // one natural row per lane; the symbols go straight to the stream
+        // (staging the 64 rows' symbols in LDS and copying them out
+        // coalesced measured slower: 470 against 370 us for the coder at
+        // 1080p)
         const int i = m.i0 + lane;
-        if (i >= m.rows_v) return;
-        int pos = off[m.row + lane];
-        bool in_run = false;
-        int run_tok = 0, run_len = 0;
-        for (int r = 0; r < m.len; ++r) {
-            const int v = x[int64_t(r) * m.rows_v + i];
-            if (v != 0) {
-                if (in_run) {
-                    out[run_tok + 1] = int16_t(run_len);
-                    in_run = false;
-                }
-                out[pos++] = int16_t(v);
-            } else {
-                if (!in_run) {
-                    in_run = true;
-                    run_tok = pos;
-                    out[pos] = 0;
-                    pos += 2;
-                    run_len = 0;
-                }
-                ++run_len;
-            }
-        }
-        if (in_run) out[run_tok + 1] = int16_t(run_len);
+        if (i < m.rows_v) rle_column(x + i, m.len, m.rows_v, out, off[m.row + lane]);
     }
 }
 
