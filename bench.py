@@ -122,13 +122,26 @@ def cpu_baseline(rgb_frames, steps_np, workers=None):
     workers = workers or max(1, min(16, os.cpu_count() or 1))
     n = min(len(jobs), 3 * workers)
     ctx = mp.get_context("spawn")
-    with ctx.Pool(workers) as pool:
-        pool.map(_oracle_plane, jobs[:workers])          # start-up and first-touch, untimed
-        t0 = time.perf_counter()
-        pool.map(_oracle_plane, jobs[:n])
-        dt = time.perf_counter() - t0
+    # one thread per worker process: the pool, not the math libraries, uses
+    # the cores (spawned workers take the environment at start)
+    thread_vars = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {v: os.environ.get(v) for v in thread_vars}
+    for v in thread_vars:
+        os.environ[v] = "1"
+    try:
+        with ctx.Pool(workers) as pool:
+            pool.map(_oracle_plane, jobs[:workers])          # start-up and first-touch, untimed
+            t0 = time.perf_counter()
+            pool.map(_oracle_plane, jobs[:n])
+            dt = time.perf_counter() - t0
+    finally:
+        for v, val in saved.items():
+            if val is None:
+                os.environ.pop(v, None)
+            else:
+                os.environ[v] = val
     return {"value": round(n / 3.0 / dt, 4), "unit": "frames/s", "cores": workers, "kind": "oracle",
-            "cpu": cpu_model(), "numpy_threads": os.environ.get("OMP_NUM_THREADS", "default"),
+            "cpu": cpu_model(), "threads_per_process": 1,
             "single_plane_latency_s": round(latency, 2),
             "single_process_frames_per_s": round(1.0 / 3.0 / latency, 4),
             "sample": f"{n} planes (Y, Co, Cg of {n // 3} 1080p frames) forward+quantise+dequantise+inverse "
