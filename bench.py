@@ -149,6 +149,29 @@ def cpu_baseline(rgb_frames, steps_np, workers=None):
                       f"plane in one process {latency:.1f} s"}
 
 
+def tuned_shapes():
+    """The split-pass tile shapes the tuner chose for the 1080p levels, from
+    its cache file: {level shape: (tree levels per pass, block height)}."""
+    path = os.environ.get("CT_AUTOTUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache",
+                                                                 "ct_autotune.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        entries = json.load(f)
+    out = {}
+    for key, code in entries.items():
+        parts = key.split("|")
+        if len(parts) != 5 or parts[1] != "split_tune" or parts[4] != f"b{PLANES}":
+            continue
+        rows, cols = (int(v) for v in parts[2].split("x"))
+        if (rows, cols) not in [((H + 15) // 16 * 16 >> j, W >> j) for j in range(J)]:
+            continue
+        mode = (code >> 4) & 3
+        height = ["default", "short", "tall", f"{((code >> 8) & 255) * 4} rows"][mode]
+        out[f"{parts[2]} {parts[3]}"] = {"levels_per_pass": code & 15, "block_height": height}
+    return out
+
+
 def ycocg_planes(rgb):
     """[B, H, W, 3] uint8 device frames -> [3B, H, W] float32 planes Y, Co + 127,
     Cg + 127 of each frame in turn (the library's colour stage, chroma factor 1)."""
@@ -393,6 +416,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-separate", action="store_true",
                     help="skip timing the four separate calls (profiling runs)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="run the step with the default tile shapes (no ct_autotune)")
     ap.add_argument("--no-extras", action="store_true",
                     help="time the step only: no colour, motion or codec stages (counter runs)")
     ap.add_argument("--mode", choices=["bench", "copy", "colour", "motion", "codec"], default="bench",
@@ -494,6 +519,14 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / args.steps, time.perf_counter() - t0
+
+    # tile shapes of the split passes, tuned once for this shape (outside the
+    # timed region; the choice does not change a bit of the output)
+    tuned = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        plan.autotune()
+        tuned = {"seconds": round(time.perf_counter() - t0, 2), "levels": tuned_shapes()}
 
     ms_sep = None
     if not args.no_separate:
@@ -611,6 +644,7 @@ def main():
         "separate_calls_ms_per_step": round(ms_sep, 4) if ms_sep else None,
         "fused_speedup_vs_separate": round(ms_sep / ms, 3) if ms_sep else None,
         "fused_bit_identical_to_separate": identical,
+        "tile_shapes": tuned,
         "wall_s": round(wall, 3),
         "roofline": roofline,
         "kernels": kernels,

@@ -255,12 +255,10 @@ int ct_inverse_adjoint(const ct_geom* geom, int32_t batch, const float* gplanes,
  * the work out in groups: the stages of one type at one chain position of
  * all streams, run by one launch that covers all their tiles. The groups
  * follow in chain order on one stream. With CT_PLAN_GRAPH the group launches
- * are captured into one HIP graph. With CT_PLAN_AUTOTUNE it times, per LP
- * level shape with three or more DFB tree levels, whether the deeper tree
- * levels stream one, two or three at a time, and with which row-block height
- * (the default, half of it or twice it), and caches the choice in a JSON file
- * (CT_AUTOTUNE_CACHE, default $HOME/.cache/ct_autotune.json); every choice
- * gives identical bits.
+ * are captured into one HIP graph. With CT_PLAN_AUTOTUNE it runs the tuner
+ * of ct_autotune on every stream's geometry; without it, a plan takes the
+ * choices an earlier tuning in this process made for its shapes, else the
+ * defaults.
  * ct_plan_run enqueues one graph launch (or the group launches) on `stream`.
  * ct_plan_run_plain enqueues the same work as separate per-stream,
  * per-stage launches (the unbatched baseline); both give identical results.
@@ -288,8 +286,9 @@ typedef struct ct_plan_info_t {
     int32_t levels_paired, levels_single;   /* LP levels with l >= 4 whose deeper tree levels run */
     int32_t levels_triple;                  /* two, one or three per pass (the tuned choice)   */
     int64_t workspace_bytes;
-    int32_t levels_short_blocks;            /* LP levels whose split passes run half-height or   */
-    int32_t levels_tall_blocks;             /* double-height row blocks (the tuned choice)       */
+    int32_t levels_short_blocks;            /* LP levels whose split passes aim at twice or half */
+    int32_t levels_tall_blocks;             /* the default wavefronts (the tuned choice), or run */
+    int32_t levels_sized_blocks;            /* blocks of explicit rows                           */
 } ct_plan_info_t;
 
 #define CT_PLAN_GRAPH 1
@@ -302,6 +301,28 @@ int ct_plan_run(ct_plan* plan, hipStream_t stream);
 int ct_plan_run_plain(ct_plan* plan, hipStream_t stream);
 int ct_plan_info(const ct_plan* plan, ct_plan_info_t* info);
 void ct_plan_destroy(ct_plan* plan);
+
+/*
+ * Tile-shape autotuning of the DFB split passes. For every LP level of `geom`
+ * with three or more DFB tree levels, times (HIP events on `stream`, waiting
+ * for them on the host) the level's split passes, analysis then synthesis, for
+ * every combination of tree levels per streaming pass (one, two or three) and
+ * row-block height (the default, the heights aiming at twice or half as many
+ * wavefronts, and heights that cut the tallest parent channel into 2..10 equal
+ * blocks), and keeps the fastest; a choice cached in the JSON file
+ * CT_AUTOTUNE_CACHE (default $HOME/.cache/ct_autotune.json) for this device
+ * architecture and shape is taken without timing. The choices go into a
+ * per-process table, keyed by device, level shape and batch, that later
+ * ct_forward, ct_inverse, their adjoints, ct_encode, ct_decode and plans
+ * without CT_PLAN_AUTOTUNE read. Every choice computes the same operations in
+ * the same order: results are identical with and without tuning.
+ *   ws, ws_bytes  a workspace of ct_workspace_bytes(geom, batch), used as
+ *                 scratch (its contents are overwritten).
+ * Returns CT_OK, CT_ERR_ARG, CT_ERR_GEOM, CT_ERR_WORKSPACE or CT_ERR_HIP.
+ * ct_autotune_clear empties the per-process table (the defaults again).
+ */
+int ct_autotune(const ct_geom* geom, int32_t batch, void* ws, size_t ws_bytes, hipStream_t stream);
+int ct_autotune_clear(void);
 
 /*
  * Encoder front end and decoder back end (paper section 2.3, Table I;

@@ -21,6 +21,7 @@ SOURCES = [
     ("ct_filters.cpp", []),
     ("ct_api.cpp", []),
     ("ct_plan.cpp", []),
+    ("ct_tune.cpp", []),
     ("ct_level.hip", ["-ffp-contract=off"]),
     ("ct_quant.hip", ["-ffp-contract=off"]),
     ("ct_batched.hip", ["-ffp-contract=off"]),

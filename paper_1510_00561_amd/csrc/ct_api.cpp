@@ -183,7 +183,13 @@ int level_block_rows(int Rj, int Cj, int batch, bool synthesis) {
     return block_rows(Rj, strips * batch, resident_waves(), 32, level_max_rows(), 8);
 }
 
-int split_block_rows(const SplitArgs& a, int batch, int levels, int height) {
+int split_block_rows(const SplitArgs& a, int batch, int levels, int height, int rows) {
+    if (height == kHeightRows && rows > 0) {
+        const int al = stream_row_align(levels);
+        int bh = (rows + al - 1) / al * al;
+        if (bh > stream_max_rows(levels)) bh = stream_max_rows(levels) / al * al;
+        return bh;
+    }
     const int t = a.t, vw = stream_cols(levels);
     const int nrh = a.Rj >> (t - 2), nch = a.Cj >> 1, nrv = a.Cj >> (t - 2), ncv = a.Rj >> 1;
     const int cols = (1 << (t - 2)) * ((nch + vw - 1) / vw + (ncv + vw - 1) / vw) * batch;
@@ -313,7 +319,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
             push(d);
             int first[4], count[4];
             const int ng = split_groups(l, tune_grouping(tune[j - 1]), first, count);
-            const int hm = tune_height(tune[j - 1]);
+            const int hm = tune_height(tune[j - 1]), hr = tune_rows(tune[j - 1]);
             float* cur = A;
             float* other = Bf;
             for (int gi = 0; gi < ng; ++gi) {
@@ -339,7 +345,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     sa.child = other;
                     sa.child_plane = RC;
                 }
-                sa.bh = split_block_rows(sa, batch, count[gi], hm);
+                sa.bh = split_block_rows(sa, batch, count[gi], hm, hr);
                 e.ntiles = split_stage_tiles(sa, batch, count[gi]);
                 const double out_b = last ? (level ? 4.0 : 0.0) + (qio.idx ? 2.0 : 0.0) : 4.0;
                 e.bytes = batch * (4.0 + out_b) * double(Rj) * Cj;
@@ -378,7 +384,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
         } else {
             int first[4], count[4];
             const int ng = split_groups(l, tune_grouping(tune[j - 1]), first, count);
-            const int hm = tune_height(tune[j - 1]);
+            const int hm = tune_height(tune[j - 1]), hr = tune_rows(tune[j - 1]);
             float* cur = A;
             float* other = Bf;
             for (int gi = ng - 1; gi >= 0; --gi) {
@@ -403,7 +409,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     sa.parent = other;
                     sa.parent_plane = RC;
                 }
-                sa.bh = split_block_rows(sa, batch, count[gi], hm);
+                sa.bh = split_block_rows(sa, batch, count[gi], hm, hr);
                 e.ntiles = split_stage_tiles(sa, batch, count[gi]);
                 const double in_b = (gi == ng - 1 && qio.idx) ? 2.0 : 4.0;
                 e.bytes = batch * (in_b + 4.0) * double(Rj) * Cj;
@@ -535,8 +541,6 @@ int launch_chain(const std::vector<StageDesc>& chain, hipStream_t st) {
 
 namespace {
 
-const int kDefaultGrouping[kMaxLevels] = {3, 3, 3, 3, 3, 3};
-
 int transform(const ct_geom* geom, int32_t batch, const float* in, float* out, void* ws,
               size_t ws_bytes, hipStream_t st, Mode mode) {
     Geometry g;
@@ -549,8 +553,9 @@ int transform(const ct_geom* geom, int32_t batch, const float* in, float* out, v
     if (!constants(g.filters).ok) return CT_ERR_UNSUPPORTED;
     if (fault_injected()) return CT_ERR_HIP;
     std::vector<StageDesc> chain;
-    build_transform_chain(g, batch, int(mode), in, out, static_cast<char*>(ws), w,
-                          kDefaultGrouping, chain);
+    int tune[kMaxLevels];
+    tuned_codes(g, batch, tune);
+    build_transform_chain(g, batch, int(mode), in, out, static_cast<char*>(ws), w, tune, chain);
     rc = launch_chain(chain, st);
     if (rc != CT_OK) return rc;
     if (mode == Mode::ForwardAdjoint) {
@@ -814,7 +819,9 @@ int ct_encode(const ct_geom* geom, int32_t batch, const float* planes, const flo
     char* wsc = static_cast<char*>(ws);
     const FusedQuant fq{idx, steps, steps_stride, nullptr};
     std::vector<StageDesc> chain;
-    build_transform_chain(g, batch, kModeForward, planes, coeffs, wsc, w, kDefaultGrouping, chain, &fq);
+    int tune[kMaxLevels];
+    tuned_codes(g, batch, tune);
+    build_transform_chain(g, batch, kModeForward, planes, coeffs, wsc, w, tune, chain, &fq);
     const float* low = coeffs ? coeffs : reinterpret_cast<const float*>(wsc + w.low_off);
     rc = build_lowpass_quant_chain(g, batch, low, coeffs ? g.ncoef : g.low_n, steps, steps_stride, idx,
                                    side, wsc, w, chain);
@@ -837,8 +844,9 @@ int ct_decode(const ct_geom* geom, int32_t batch, const int16_t* idx, const floa
     if (fault_injected()) return CT_ERR_HIP;
     const FusedQuant fq{const_cast<int16_t*>(idx), steps, steps_stride, side};
     std::vector<StageDesc> chain;
-    build_transform_chain(g, batch, kModeInverse, nullptr, planes, static_cast<char*>(ws), w,
-                          kDefaultGrouping, chain, &fq);
+    int tune[kMaxLevels];
+    tuned_codes(g, batch, tune);
+    build_transform_chain(g, batch, kModeInverse, nullptr, planes, static_cast<char*>(ws), w, tune, chain, &fq);
     return launch_chain(chain, stream);
 }
 

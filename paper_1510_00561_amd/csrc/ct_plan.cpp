@@ -58,190 +58,14 @@ struct ct_plan {
 
 namespace {
 
-// ---------------------------------------------------------------- autotune cache
-std::string cache_path() {
-    const char* p = getenv("CT_AUTOTUNE_CACHE");
-    if (p && *p) return p;
-    const char* home = getenv("HOME");
-    return std::string(home ? home : ".") + "/.cache/ct_autotune.json";
-}
-
-// The cache is a flat JSON object {"key": integer, ...}.
-std::map<std::string, int> load_cache() {
-    std::map<std::string, int> m;
-    FILE* f = fopen(cache_path().c_str(), "r");
-    if (!f) return m;
-    std::string text;
-    char buf[4096];
-    size_t n;
-    while ((n = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, n);
-    fclose(f);
-    size_t i = 0;
-    while ((i = text.find('"', i)) != std::string::npos) {
-        const size_t j = text.find('"', i + 1);
-        if (j == std::string::npos) break;
-        const std::string key = text.substr(i + 1, j - i - 1);
-        const size_t colon = text.find(':', j);
-        if (colon == std::string::npos) break;
-        m[key] = atoi(text.c_str() + colon + 1);
-        i = text.find_first_of(",}", colon);
-        if (i == std::string::npos) break;
-    }
-    return m;
-}
-
-void save_cache(const std::map<std::string, int>& m) {
-    const std::string path = cache_path();
-    const size_t slash = path.rfind('/');
-    if (slash != std::string::npos) mkdir(path.substr(0, slash).c_str(), 0755);   // may exist
-    FILE* f = fopen(path.c_str(), "w");
-    if (!f) return;   // no writable cache: the choices stay in this plan only
-    fprintf(f, "{\n");
-    size_t k = 0;
-    for (const auto& kv : m) fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++k < m.size() ? "," : "");
-    fprintf(f, "}\n");
-    fclose(f);
-}
-
-std::string arch_name(int dev) {
-    hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
-    return p.gcnArchName;
-}
-
-// Time the DFB split passes (analysis then synthesis) of one LP level shape
-// with the given grouping and block height, using workspace buffers as
-// scratch.
-float time_level_splits(int Rj, int Cj, int l, int batch, int grouping, int height, float* A, float* B,
-                        float* D, int64_t plane, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    int first[4], count[4], ng = 0;
-    for (int t = 3; t <= l;) {
-        const int c = t + grouping - 1 <= l ? grouping : l - t + 1;
-        first[ng] = t;
-        count[ng] = c;
-        ++ng;
-        t += c;
-    }
-    static hipError_t (*const ana[3])(const SplitArgs&, Lift, int, hipStream_t) = {
-        launch_dfb_split_analysis, launch_dfb_split2_analysis, launch_dfb_split3_analysis};
-    static hipError_t (*const syn[3])(const SplitArgs&, Lift, int, hipStream_t) = {
-        launch_dfb_split_synthesis, launch_dfb_split2_synthesis, launch_dfb_split3_synthesis};
-    Lift L{{-1.5f, -0.05f, 0.88f, 0.44f}, 1};
-    auto run = [&]() -> bool {
-        float* cur = A;
-        float* other = B;
-        for (int gi = 0; gi < ng; ++gi) {
-            SplitArgs a;
-            memset(&a, 0, sizeof(a));
-            a.t = first[gi];
-            a.Rj = Rj;
-            a.Cj = Cj;
-            a.parent = cur;
-            a.parent_plane = plane;
-            a.child = gi == ng - 1 ? D : other;
-            a.child_plane = plane;
-            a.plane_elems = int64_t(Rj) * Cj;
-            a.bh = split_block_rows(a, batch, count[gi], height);
-            hipError_t e = ana[count[gi] - 1](a, L, batch, st);
-            if (e != hipSuccess) return false;
-            std::swap(cur, other);
-        }
-        float* cur2 = A;
-        float* other2 = B;
-        for (int gi = ng - 1; gi >= 0; --gi) {
-            SplitArgs a;
-            memset(&a, 0, sizeof(a));
-            a.t = first[gi];
-            a.Rj = Rj;
-            a.Cj = Cj;
-            a.parent = gi == ng - 1 ? D : other2;
-            a.parent_plane = plane;
-            a.child = cur2;
-            a.child_plane = plane;
-            a.plane_elems = int64_t(Rj) * Cj;
-            a.bh = split_block_rows(a, batch, count[gi], height);
-            hipError_t e = syn[count[gi] - 1](a, L, batch, st);
-            if (e != hipSuccess) return false;
-            std::swap(cur2, other2);
-        }
-        return true;
-    };
-    if (!run()) return -1.f;
-    if (hipEventRecord(e0, st) != hipSuccess) return -1.f;
-    for (int r = 0; r < 3; ++r)
-        if (!run()) return -1.f;
-    if (hipEventRecord(e1, st) != hipSuccess) return -1.f;
-    if (hipEventSynchronize(e1) != hipSuccess) return -1.f;
-    float ms = 0;
-    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
-    return ms;
-}
-
-// A cached code the chain builder can use (anything else is tuned again).
-bool valid_tune(int code) {
-    const int g = tune_grouping(code), h = tune_height(code);
-    return code >= 0 && (code >> 6) == 0 && g >= 1 && g <= 3 && h <= kHeightTall;
-}
-
 int autotune(ct_plan* p, hipStream_t st) {
-    std::map<std::string, int> cache = load_cache();
-    const std::string arch = arch_name(p->device);
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return CT_ERR_HIP;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
-        return CT_ERR_HIP;
+    for (size_t s = 0; s < p->streams.size(); ++s) {
+        const int rc = tune_geometry(p->geoms[s], p->streams[s].batch, p->ws + p->ws_off[s], p->wls[s], st,
+                                     &p->grouping[s * kMaxLevels]);
+        if (rc != CT_OK) return rc;
     }
-    bool dirty = false;
-    int rc = CT_OK;
-    for (size_t s = 0; s < p->streams.size() && rc == CT_OK; ++s) {
-        const Geometry& g = p->geoms[s];
-        const int batch = p->streams[s].batch;
-        char* ws = p->ws + p->ws_off[s];
-        const Workspace& w = p->wls[s];
-        for (int j = 1; j <= g.J; ++j) {
-            const int l = g.l[j - 1];
-            if (l < 3) continue;    // no split pass
-            const int Rj = g.R >> (j - 1), Cj = g.C >> (j - 1);
-            char key[160];
-            snprintf(key, sizeof(key), "%s|split_tune|%dx%d|l%d|b%d", arch.c_str(), Rj, Cj, l, batch);
-            auto it = cache.find(key);
-            int choice;
-            if (it != cache.end() && valid_tune(it->second)) {
-                choice = it->second;
-            } else {
-                float* A = reinterpret_cast<float*>(ws + w.a_off);
-                float* B = reinterpret_cast<float*>(ws + w.b_off);
-                float* D = reinterpret_cast<float*>(ws + w.d_off);
-                const int64_t plane = int64_t(g.R) * g.C;
-                // every grouping that differs for this depth (up to l - 2
-                // levels per pass), at each of the three block heights
-                float best = -1.f;
-                choice = tune_code(1, kHeightDefault);
-                for (int grp = 1; grp <= 3 && grp <= l - 2 && rc == CT_OK; ++grp)
-                    for (int hm = kHeightDefault; hm <= kHeightTall; ++hm) {
-                        const float ms = time_level_splits(Rj, Cj, l, batch, grp, hm, A, B, D, plane, st, e0, e1);
-                        if (ms < 0) {
-                            rc = CT_ERR_HIP;
-                            break;
-                        }
-                        if (best < 0 || ms < best) {
-                            best = ms;
-                            choice = tune_code(grp, hm);
-                        }
-                    }
-                if (rc != CT_OK) break;
-                cache[key] = choice;
-                dirty = true;
-            }
-            p->grouping[s * kMaxLevels + (j - 1)] = choice;
-        }
-    }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    if (dirty) save_cache(cache);
     p->autotuned = 1;
-    return rc;
+    return CT_OK;
 }
 
 // The group launches of a plan, in chain order.
@@ -316,6 +140,9 @@ int ct_plan_create(const ct_stream_desc* streams, int32_t n, int32_t flags, ct_p
             free_plan(p);
             return rc;
         }
+    } else {
+        // choices an earlier tuning in this process made for these shapes
+        for (int s = 0; s < n; ++s) tuned_codes(p->geoms[s], streams[s].batch, &p->grouping[size_t(s) * kMaxLevels]);
     }
     // per-stream chains
     p->chains.resize(n);
@@ -435,7 +262,7 @@ int ct_plan_info(const ct_plan* p, ct_plan_info_t* info) {
     info->launches = int32_t(p->groups.size());
     info->graph = p->exec ? 1 : 0;
     info->autotuned = p->autotuned;
-    int n[4] = {0, 0, 0, 0}, h[3] = {0, 0, 0};
+    int n[4] = {0, 0, 0, 0}, h[4] = {0, 0, 0, 0};
     for (size_t s = 0; s < p->streams.size(); ++s)
         for (int j = 0; j < p->geoms[s].J; ++j) {
             const int l = p->geoms[s].l[j];
@@ -450,6 +277,7 @@ int ct_plan_info(const ct_plan* p, ct_plan_info_t* info) {
     info->levels_triple = n[3];
     info->levels_short_blocks = h[kHeightShort];
     info->levels_tall_blocks = h[kHeightTall];
+    info->levels_sized_blocks = h[kHeightRows];
     info->workspace_bytes = 0;
     for (size_t s = 0; s < p->streams.size(); ++s) info->workspace_bytes += p->wls[s].total;
     return CT_OK;

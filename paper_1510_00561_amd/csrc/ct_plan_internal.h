@@ -43,12 +43,24 @@ struct FusedQuant {
 };
 // Per-LP-level tuning of the split passes, one int per level: the DFB tree
 // levels per pass (bits 0-3: 1, 2 or 3) and the row-block height (bits 4-5:
-// kHeightDefault, kHeightShort = about half the rows, kHeightTall = about
-// twice). Every code computes the same operations in the same order.
-enum { kHeightDefault = 0, kHeightShort = 1, kHeightTall = 2 };
+// kHeightDefault, kHeightShort = aiming at twice the wavefronts, kHeightTall =
+// at half of them, kHeightRows = the explicit rows of bits 8-15, in units of
+// 4). Every code computes the same operations in the same order.
+enum { kHeightDefault = 0, kHeightShort = 1, kHeightTall = 2, kHeightRows = 3 };
+constexpr int kDefaultTune = 3;     // three tree levels per pass, default height
 inline int tune_grouping(int code) { return code & 15; }
 inline int tune_height(int code) { return (code >> 4) & 3; }
-inline int tune_code(int grouping, int height) { return grouping | (height << 4); }
+inline int tune_rows(int code) { return ((code >> 8) & 255) * 4; }
+inline int tune_code(int grouping, int height, int rows = 0) { return grouping | (height << 4) | ((rows / 4) << 8); }
+// A code the chain builder accepts (a cached value outside this is tuned again).
+bool valid_tune(int code);
+// The tuned codes of every LP level of g at this batch on the current device
+// (kDefaultTune where nothing was tuned in this process).
+void tuned_codes(const Geometry& g, int batch, int* codes /* [kMaxLevels] */);
+// Tunes every LP level of g with three or more DFB tree levels (or takes the
+// cached choice), using the workspace as scratch, and records the choices in
+// the per-process table; codes[j - 1] receives level j's code.
+int tune_geometry(const Geometry& g, int batch, char* ws, const Workspace& w, hipStream_t st, int* codes);
 void build_transform_chain(const Geometry& g, int batch, int mode, const float* in, float* out,
                            char* ws, const Workspace& w, const int* tune,
                            std::vector<StageDesc>& chain, const FusedQuant* fq = nullptr);
@@ -69,7 +81,7 @@ int fill_quant_args(const Geometry& g, QuantArgs* a);
 int resident_waves();
 // Rows per streamed block of an LP-level stage and of a split stage.
 int level_block_rows(int Rj, int Cj, int batch, bool synthesis);
-int split_block_rows(const SplitArgs& a, int batch, int levels, int height = kHeightDefault);
+int split_block_rows(const SplitArgs& a, int batch, int levels, int height = kHeightDefault, int rows = 0);
 
 // Work-queue tiles of an LP-level stage (one wavefront item per strip and
 // row block, kBatchedThreads / 64 per tile).

@@ -69,7 +69,8 @@ class PlanInfo(ctypes.Structure):
                 ("graph", ctypes.c_int32), ("autotuned", ctypes.c_int32),
                 ("levels_paired", ctypes.c_int32), ("levels_single", ctypes.c_int32),
                 ("levels_triple", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
-                ("levels_short_blocks", ctypes.c_int32), ("levels_tall_blocks", ctypes.c_int32)]
+                ("levels_short_blocks", ctypes.c_int32), ("levels_tall_blocks", ctypes.c_int32),
+                ("levels_sized_blocks", ctypes.c_int32)]
 
 
 PLAN_GRAPH = 1
@@ -118,6 +119,8 @@ def _lib():
             "ct_rle_decode_host": [G, P, P, i32, P],
             "ct_deflate_host": [P, P, i32, i32, i32, P, sz, P, ctypes.POINTER(sz)],
             "ct_inflate_host": [P, P, P, i32, i32, P],
+            "ct_autotune": [G, i32, P, sz, P],
+            "ct_autotune_clear": [],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -186,6 +189,11 @@ def profile_collect(alg=False):
     return res
 
 
+def autotune_clear():
+    """Forget this process's tuned tile shapes (ct_autotune_clear)."""
+    _check("ct_autotune_clear", _lib().ct_autotune_clear())
+
+
 def workspace_bytes(height, width, levels, dirs, batch):
     g = geom(height, width, levels, dirs)
     n = ctypes.c_size_t(0)
@@ -248,6 +256,14 @@ class Plan:
     def inverse_adjoint(self, gplanes, out=None):
         B, H, W = self.batch, self.height, self.width
         return self._io("ct_inverse_adjoint", gplanes, (B, H, W), (B, self.ncoef), out)
+
+    def autotune(self):
+        """Tune the split passes' tile shapes for this geometry and batch
+        (ct_autotune); later calls of every plan of this shape in this process
+        use the choices. Returns nothing; blocks until the timing is done."""
+        _check("ct_autotune", _lib().ct_autotune(ctypes.byref(self.g), self.batch,
+                                                 ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                                 self._stream()))
 
     def _steps(self, steps):
         if steps.dim() == 1:

@@ -231,3 +231,20 @@ def test_variant_fields_validated(ct):
         assert lib.ct_workspace_bytes(ctypes.byref(g), 2, ctypes.byref(n)) == -2
         d = ctypes.c_void_p(0x1000)
         assert lib.ct_forward(ctypes.byref(g), 1, d, d, d, 1 << 30, None) == -2
+
+
+def test_autotune_validation(ct):
+    """ct_autotune checks its arguments before any HIP call."""
+    lib = ct._lib()
+    g = ct.geom(256, 256, 2, [32, 4])
+    d = ctypes.c_void_p(0x1000)
+    n = ctypes.c_size_t(0)
+    assert lib.ct_workspace_bytes(ctypes.byref(g), 2, ctypes.byref(n)) == 0
+    assert lib.ct_autotune(None, 1, d, n.value, None) == -1
+    assert lib.ct_autotune(ctypes.byref(g), -1, d, n.value, None) == -1
+    assert lib.ct_autotune(ctypes.byref(g), 0, None, 0, None) == 0          # empty batch
+    assert lib.ct_autotune(ctypes.byref(g), 2, None, n.value, None) == -1
+    assert lib.ct_autotune(ctypes.byref(g), 2, d, n.value - 1, None) == -3
+    bad = ct.geom(256, 256, 2, [32, 6])
+    assert lib.ct_autotune(ctypes.byref(bad), 2, d, n.value, None) == -2
+    assert lib.ct_autotune_clear() == 0

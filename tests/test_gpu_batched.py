@@ -123,6 +123,16 @@ def test_batched_parity_with_oracle():
     plan.close()
 
 
+@pytest.fixture(autouse=True)
+def _forget_tuning():
+    """Tuned tile shapes live in a per-process table: start and leave every
+    test of this file with the defaults."""
+    from paper_1510_00561_amd import ct
+    ct.autotune_clear()
+    yield
+    ct.autotune_clear()
+
+
 def _tune_keys(streams):
     """(autotune cache key, l) of every LP level with three or more DFB tree
     levels in `streams` (the levels that run split passes), one entry per
@@ -140,7 +150,12 @@ def _tune_keys(streams):
 
 
 def _valid_code(v):
-    return 1 <= (v & 15) <= 3 and (v >> 4) in (0, 1, 2)
+    """Tree levels per pass in bits 0-3, block height mode in bits 4-5 (0
+    default, 1 short, 2 tall, 3 explicit rows in bits 8-15, units of 4)."""
+    grp, hm, rows = v & 15, (v >> 4) & 3, ((v >> 8) & 255) * 4
+    if v >> 16 or v & 0xc0 or not 1 <= grp <= 3:
+        return False
+    return 32 <= rows <= 1020 if hm == 3 else rows == 0
 
 
 def test_autotuned_plan(tmp_path, monkeypatch):
@@ -176,14 +191,15 @@ def test_split_tile_shapes_are_bit_identical(tmp_path, monkeypatch):
     assert deep
     snaps = []
     # codes: tree levels per pass in bits 0-3, block height in bits 4-5
-    # (0 default, 1 short, 2 tall)
-    for code in (1, 2, 3, 1 | 16, 3 | 16, 2 | 32, 3 | 32):
+    # (0 default, 1 short, 2 tall, 3 explicit rows / 4 in bits 8-15)
+    for code in (1, 2, 3, 1 | 16, 3 | 16, 2 | 32, 3 | 32, 3 | 48 | (192 // 4) << 8, 1 | 48 | (32 // 4) << 8,
+                 2 | 48 | (248 // 4) << 8):
         cache = tmp_path / f"forced{code}.json"
         cache.write_text(json.dumps({k: code for k, _ in keys}))
         monkeypatch.setenv("CT_AUTOTUNE_CACHE", str(cache))
         plan = ct.Batched(_streams(5), graph=True, autotune=True)
         info = plan.info()
-        grp, hm = code & 15, code >> 4
+        grp, hm = code & 15, (code >> 4) & 3
         # a level with l tree levels runs at most l - 2 of them per pass
         want = {1: 0, 2: 0, 3: 0}
         for l in deep:
@@ -191,6 +207,7 @@ def test_split_tile_shapes_are_bit_identical(tmp_path, monkeypatch):
         assert (info["levels_single"], info["levels_paired"], info["levels_triple"]) == (want[1], want[2], want[3])
         assert info["levels_short_blocks"] == (len(keys) if hm == 1 else 0)
         assert info["levels_tall_blocks"] == (len(keys) if hm == 2 else 0)
+        assert info["levels_sized_blocks"] == (len(keys) if hm == 3 else 0)
         plan.run()
         torch.cuda.synchronize()
         snaps.append(_snapshot(plan))
@@ -223,3 +240,34 @@ def test_fused_plan_equals_encode_decode():
         assert torch.equal(g["idx"], idx) and torch.equal(g["side"], side)
         assert torch.equal(g["out"], out)
     plan.close()
+
+
+def test_per_call_autotune_keeps_the_bits(tmp_path, monkeypatch):
+    """ct_autotune records tile shapes that the per-call entry points then use:
+    the transform and the fused codec give the same bits before and after, and
+    a plan built afterwards without tuning takes the same choices."""
+    from paper_1510_00561_amd import ct
+    monkeypatch.setenv("CT_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    ct.autotune_clear()
+    H, W, J, dirs, B = 240, 320, 2, [32, 16], 3
+    x = torch.from_numpy(np.random.default_rng(5).uniform(0, 255, (B, H, W)).astype(np.float32)).cuda()
+    steps = torch.from_numpy(np.random.default_rng(6).integers(4, 65, ct.layout(H, W, J, dirs)[0].nsub)
+                             .astype(np.float32)).cuda()
+    plan = ct.Plan(H, W, J, dirs, B, "cuda")
+    coef0 = plan.forward(x).clone()
+    idx0, side0 = (t.clone() for t in plan.encode(x, steps))
+    out0 = plan.decode(idx0, steps, side0).clone()
+    plan.autotune()
+    entries = json.loads((tmp_path / "tune.json").read_text())
+    assert len(entries) == 2 and all(_valid_code(v) for v in entries.values())
+    coef1 = plan.forward(x)
+    idx1, side1 = plan.encode(x, steps)
+    out1 = plan.decode(idx1, steps, side1)
+    torch.cuda.synchronize()
+    assert torch.equal(coef0, coef1) and torch.equal(idx0, idx1) and torch.equal(out0, out1)
+    steps_b = steps.unsqueeze(0).expand(B, -1).contiguous()
+    bt = ct.Batched([dict(height=H, width=W, levels=J, dirs=dirs, planes=x, steps=steps_b)], graph=True)
+    info = bt.info()
+    tuned = sum(1 for v in entries.values() if (v >> 4) & 3)
+    assert info["levels_short_blocks"] + info["levels_tall_blocks"] + info["levels_sized_blocks"] == tuned
+    bt.close()
