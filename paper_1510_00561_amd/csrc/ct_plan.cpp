@@ -7,22 +7,15 @@
 // the group launches. A group is the set of stages of one type at one chain
 // position over all streams; its launch covers all their tiles.
 //
-// Autotuning (CT_PLAN_AUTOTUNE) picks, for every distinct LP level shape
-// with three or more DFB tree levels, how many of the deeper tree levels run
-// per streaming pass (one, two or three: halo 4, 12 or 28 rows) and the
-// row-block height of those passes (the host's default, about half of it or
-// about twice it), by timing every combination with HIP events. All choices
-// compute the same float32 operations in the same order, so none changes a
-// result. Choices are cached in a JSON file keyed by device architecture and
-// shape (CT_AUTOTUNE_CACHE, default $HOME/.cache/ct_autotune.json).
+// With CT_PLAN_AUTOTUNE every stream's geometry goes through the tile-shape
+// tuner of the split passes (ct_tune.cpp); without it the plan takes the
+// choices an earlier tuning in this process made, else the defaults. No
+// choice changes a result.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
-#include <sys/stat.h>
 
 #include <algorithm>
-#include <map>
-#include <string>
 #include <vector>
 
 #include "ct_batched.h"
