@@ -460,8 +460,10 @@ int ct_mc_residual(const ct_geom* geom, int32_t batch, int32_t n, const int16_t*
  *             component within its plane's stream, then the plane's count.
  *   ws        workspace of ct_rle_workspace_bytes() bytes.
  * ct_rle_decode_host is the decoder (host code, one plane, host pointers):
- * it parses every component's rows and returns CT_ERR_ARG for a stream
- * that does not parse to exactly the layout.
+ * symbols holds sub_off[nsub] symbols. It checks first that sub_off starts
+ * at or above 0 and never decreases, then parses every component's rows, and
+ * returns CT_ERR_ARG for offsets or a stream that do not parse to exactly the
+ * layout; it reads no symbol outside [sub_off[0], sub_off[nsub]).
  */
 int ct_rle_workspace_bytes(const ct_geom* geom, int32_t batch, size_t* bytes);
 int ct_rle_encode(const ct_geom* geom, int32_t batch, const int16_t* idx, int32_t p_frame,
@@ -477,7 +479,9 @@ int ct_rle_decode_host(const ct_geom* geom, const int16_t* symbols, const int32_
  * once (CVC-NTS: comp_bytes[0]). The symbols are taken as little-endian
  * int16 bytes. *total receives the bytes written; CT_ERR_WORKSPACE if cap
  * is too small (cap = sum of compressBound over the parts always suffices).
- * ct_inflate_host is the inverse; it needs sub_off to size every part.
+ * ct_inflate_host is the inverse; it needs sub_off to size every part, and
+ * `in` holds the sum of comp_bytes over the parts. Both return CT_ERR_ARG
+ * when sub_off is negative or decreasing (checked before any access).
  */
 int ct_deflate_host(const int16_t* symbols, const int32_t* sub_off, int32_t nsub, int32_t mode,
                     int32_t level, uint8_t* out, size_t cap, uint32_t* comp_bytes, size_t* total);

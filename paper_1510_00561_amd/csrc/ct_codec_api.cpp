@@ -94,6 +94,16 @@ struct Comp {
     int64_t offset;
 };
 
+// Offsets of a plane's stream: non-negative and non-decreasing, so that every
+// component lies inside the sub_off[n] symbols the caller holds. Checked in
+// full before any symbol is touched.
+bool offsets_ok(const int32_t* sub_off, int n) {
+    if (sub_off[0] < 0) return false;
+    for (int s = 0; s < n; ++s)
+        if (sub_off[s + 1] < sub_off[s]) return false;
+    return true;
+}
+
 std::vector<Comp> components(const ct::Geometry& g, int p_frame) {
     std::vector<ct_subband> tab(g.nsub);
     ct::subband_table(g, tab.data(), g.nsub);
@@ -189,6 +199,7 @@ int ct_rle_decode_host(const ct_geom* geom, const int16_t* symbols, const int32_
     const int rc = geometry(geom, 1, &g);
     if (rc != CT_OK) return rc;
     if (!symbols || !sub_off || !idx) return CT_ERR_ARG;
+    if (!offsets_ok(sub_off, g.nsub)) return CT_ERR_ARG;
     const std::vector<Comp> comps = components(g, p_frame);
     for (int s = 0; s < g.nsub; ++s) {
         const Comp& c = comps[s];
@@ -228,6 +239,7 @@ int ct_deflate_host(const int16_t* symbols, const int32_t* sub_off, int32_t nsub
     if (total) *total = 0;
     if (!symbols || !sub_off || !comp_bytes || !total || nsub < 1 || (mode != 0 && mode != 1)) return CT_ERR_ARG;
     if (level < 0 || level > 9 || (cap > 0 && !out)) return CT_ERR_ARG;
+    if (!offsets_ok(sub_off, nsub)) return CT_ERR_ARG;
     const int parts = mode == 0 ? nsub : 1;
     size_t used = 0;
     for (int s = 0; s < parts; ++s) {
@@ -249,6 +261,7 @@ int ct_deflate_host(const int16_t* symbols, const int32_t* sub_off, int32_t nsub
 int ct_inflate_host(const uint8_t* in, const uint32_t* comp_bytes, const int32_t* sub_off, int32_t nsub,
                     int32_t mode, int16_t* symbols) {
     if (!in || !comp_bytes || !sub_off || !symbols || nsub < 1 || (mode != 0 && mode != 1)) return CT_ERR_ARG;
+    if (!offsets_ok(sub_off, nsub)) return CT_ERR_ARG;
     const int parts = mode == 0 ? nsub : 1;
     size_t used = 0;
     for (int s = 0; s < parts; ++s) {
