@@ -248,8 +248,12 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
     const Taps5 zero{};
     const int64_t RC = int64_t(g.R) * g.C;
     float* D = reinterpret_cast<float*>(ws + w.d_off);
-    float* A = reinterpret_cast<float*>(ws + w.a_off);
-    float* Bf = reinterpret_cast<float*>(ws + w.b_off);
+    // channel buffers of LP level j: level 1 has its own pair, the coarser
+    // levels share a second one (a plane of it holds R C / 4 floats)
+    float* const A1 = reinterpret_cast<float*>(ws + w.a_off);
+    float* const B1 = reinterpret_cast<float*>(ws + w.b_off);
+    float* const A2 = reinterpret_cast<float*>(ws + w.a2_off);
+    float* const B2 = reinterpret_cast<float*>(ws + w.b2_off);
     auto push = [&](StageDesc d) {
         d.batch = batch;
         d.lift = L;
@@ -284,6 +288,9 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
             a.R = Rj;
             a.C = Cj;
             const int l = g.l[j - 1];
+            float* const A = j == 1 ? A1 : A2;
+            float* const Bf = j == 1 ? B1 : B2;
+            const int64_t PS = j == 1 ? RC : RC / 4;     // plane stride of the channel buffers
             float* level = coeffs ? coeffs + g.level_off[j] : nullptr;
             const int64_t q4 = int64_t(Rj) * Cj / 4;
             const QuantIO qio = fq ? QuantIO{fq->idx + g.level_off[j], g.ncoef, fq->steps, fq->steps_stride,
@@ -295,7 +302,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                 a.out.p[k] = l == 2 ? (level ? level + k * q4 : nullptr) : A + k * q4;
                 a.out.scale[k] = l == 2 ? sc[k] : 1.f;
             }
-            a.out.plane = l == 2 ? g.ncoef : RC;
+            a.out.plane = l == 2 ? g.ncoef : PS;
             if (l == 2 && qio.idx) {
                 a.q = qio;
                 d.type = kStLevelAnaQ;
@@ -332,7 +339,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                 sa.Rj = Rj;
                 sa.Cj = Cj;
                 sa.parent = cur;
-                sa.parent_plane = RC;
+                sa.parent_plane = PS;
                 sa.plane_elems = int64_t(Rj) * Cj;
                 if (last) {
                     sa.child = level;
@@ -343,7 +350,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     if (qio.idx) e.type = split_type(count[gi], true, true);
                 } else {
                     sa.child = other;
-                    sa.child_plane = RC;
+                    sa.child_plane = PS;
                 }
                 sa.bh = split_block_rows(sa, batch, count[gi], hm, hr);
                 e.ntiles = split_stage_tiles(sa, batch, count[gi]);
@@ -362,6 +369,9 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
     for (int j = g.J; j >= 1; --j) {
         const int Rj = g.R >> (j - 1), Cj = g.C >> (j - 1);
         const int l = g.l[j - 1];
+        float* const A = j == 1 ? A1 : A2;
+        float* const Bf = j == 1 ? B1 : B2;
+        const int64_t PS = j == 1 ? RC : RC / 4;
         const float* level = coeffs ? coeffs + g.level_off[j] : nullptr;
         const int64_t q4 = int64_t(Rj) * Cj / 4;
         const QuantIO qio = fq ? QuantIO{const_cast<int16_t*>(fq->idx) + g.level_off[j], g.ncoef, fq->steps,
@@ -397,7 +407,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                 sa.Cj = Cj;
                 sa.plane_elems = int64_t(Rj) * Cj;
                 sa.child = cur;             // output: the parents
-                sa.child_plane = RC;
+                sa.child_plane = PS;
                 if (gi == ng - 1) {
                     sa.parent = level;      // input: the final subbands
                     sa.parent_plane = g.ncoef;
@@ -407,7 +417,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                     if (qio.idx) e.type = split_type(count[gi], false, true);
                 } else {
                     sa.parent = other;
-                    sa.parent_plane = RC;
+                    sa.parent_plane = PS;
                 }
                 sa.bh = split_block_rows(sa, batch, count[gi], hm, hr);
                 e.ntiles = split_stage_tiles(sa, batch, count[gi]);
@@ -423,7 +433,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                 a.in.p[k] = other + k * q4;
                 a.in.scale[k] = 1.f;
             }
-            a.in.plane = RC;
+            a.in.plane = PS;
         }
         a.c_in = (j == g.J)
                      ? CView{coeffs, g.ncoef, Cj / 2}
@@ -537,6 +547,98 @@ int launch_chain(const std::vector<StageDesc>& chain, hipStream_t st) {
     return CT_OK;
 }
 
+namespace {
+
+// A second stream per device, and a fork and a join event, for chains whose
+// level-1 split passes run beside the coarser levels. Created at first use
+// and kept until the process ends; default priority, non-blocking.
+struct Side {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_side_mu;
+Side g_side[64];
+
+bool is_level_stage(const StageDesc& d) {
+    return d.type == kStLevelAna || d.type == kStLevelAnaQ || d.type == kStLevelSyn || d.type == kStLevelSynQ;
+}
+bool is_split_stage(const StageDesc& d) {
+    switch (d.type) {
+        case kStSplit1Ana: case kStSplit2Ana: case kStSplit3Ana: case kStSplit1AnaQ: case kStSplit2AnaQ:
+        case kStSplit3AnaQ: case kStSplit1Syn: case kStSplit2Syn: case kStSplit3Syn: case kStSplit1SynQ:
+        case kStSplit2SynQ: case kStSplit3SynQ:
+            return true;
+        default:
+            return false;
+    }
+}
+
+}  // namespace
+
+// The level-1 split passes of a transform chain (stages [a0, a1)) depend only
+// on the level-1 LP stage of the analysis (stage 0), or on nothing in the
+// synthesis, and nothing but the level-1 LP synthesis (stage a1) depends on
+// them; the coarser levels use their own channel buffers. So they run on a
+// second stream beside the rest of the chain: the device overlaps the long
+// level-1 passes with the short, latency-bound coarse levels. The results
+// are those of launch_chain (each stage computes the same operations).
+int launch_chain_forked(const std::vector<StageDesc>& chain, hipStream_t st) {
+    const char* serial = getenv("CT_SERIAL_LEVELS");
+    if (serial && *serial == '1') return launch_chain(chain, st);
+    // find the level-1 split passes: analysis, right after the first LP
+    // stage; synthesis, right before the last one
+    const size_t n = chain.size();
+    size_t a0 = 0, a1 = 0;
+    bool analysis = false;
+    if (n > 2 && (chain[0].type == kStLevelAna || chain[0].type == kStLevelAnaQ)) {
+        analysis = true;
+        a0 = a1 = 1;
+        while (a1 < n && is_split_stage(chain[a1])) ++a1;
+        if (a1 == n || !is_level_stage(chain[a1])) return launch_chain(chain, st);   // a single level
+    } else if (n > 2 && (chain[n - 1].type == kStLevelSyn || chain[n - 1].type == kStLevelSynQ)) {
+        a1 = n - 1;
+        a0 = a1;
+        while (a0 > 0 && is_split_stage(chain[a0 - 1])) --a0;
+        if (a0 == 0) return launch_chain(chain, st);                                  // a single level
+    } else {
+        return launch_chain(chain, st);
+    }
+    if (a0 == a1) return launch_chain(chain, st);                                     // no level-1 split
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return CT_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    Side& side = g_side[dev];
+    if (!side.s) {
+        if (hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking) != hipSuccess) return CT_ERR_HIP;
+        if (hipEventCreateWithFlags(&side.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&side.join, hipEventDisableTiming) != hipSuccess)
+            return CT_ERR_HIP;
+    }
+    auto run = [&](size_t b, size_t e, hipStream_t s) -> int {
+        for (size_t i = b; i < e; ++i) {
+            const int rc = launch_stage(chain[i], s);
+            if (rc != CT_OK) return rc;
+        }
+        return CT_OK;
+    };
+    // analysis: stage 0 on the caller's stream first; then the level-1
+    // passes on the side stream and the coarser levels on the caller's.
+    // synthesis: the level-1 passes on the side stream from the start, the
+    // coarser levels on the caller's, both joined before the last LP stage.
+    int rc = analysis ? run(0, 1, st) : CT_OK;
+    if (rc != CT_OK) return rc;
+    if (hipEventRecord(side.fork, st) != hipSuccess || hipStreamWaitEvent(side.s, side.fork, 0) != hipSuccess)
+        return CT_ERR_HIP;
+    rc = run(a0, a1, side.s);
+    // the join is enqueued whatever happened, so that the caller's stream
+    // never runs ahead of work left on the side stream
+    const bool joined = hipEventRecord(side.join, side.s) == hipSuccess;
+    if (rc == CT_OK) rc = analysis ? run(a1, n, st) : run(0, a0, st);
+    if (!joined || hipStreamWaitEvent(st, side.join, 0) != hipSuccess) return CT_ERR_HIP;
+    if (rc == CT_OK && !analysis) rc = run(a1, n, st);
+    return rc;
+}
+
 }  // namespace ct
 
 namespace {
@@ -556,7 +658,7 @@ int transform(const ct_geom* geom, int32_t batch, const float* in, float* out, v
     int tune[kMaxLevels];
     tuned_codes(g, batch, tune);
     build_transform_chain(g, batch, int(mode), in, out, static_cast<char*>(ws), w, tune, chain);
-    rc = launch_chain(chain, st);
+    rc = launch_chain_forked(chain, st);
     if (rc != CT_OK) return rc;
     if (mode == Mode::ForwardAdjoint) {
         const int64_t RC = int64_t(g.R) * g.C;
@@ -826,7 +928,7 @@ int ct_encode(const ct_geom* geom, int32_t batch, const float* planes, const flo
     rc = build_lowpass_quant_chain(g, batch, low, coeffs ? g.ncoef : g.low_n, steps, steps_stride, idx,
                                    side, wsc, w, chain);
     if (rc != CT_OK) return rc;
-    return launch_chain(chain, stream);
+    return launch_chain_forked(chain, stream);
 }
 
 int ct_decode(const ct_geom* geom, int32_t batch, const int16_t* idx, const float* steps,
@@ -847,7 +949,7 @@ int ct_decode(const ct_geom* geom, int32_t batch, const int16_t* idx, const floa
     int tune[kMaxLevels];
     tuned_codes(g, batch, tune);
     build_transform_chain(g, batch, kModeInverse, nullptr, planes, static_cast<char*>(ws), w, tune, chain, &fq);
-    return launch_chain(chain, stream);
+    return launch_chain_forked(chain, stream);
 }
 
 int ct_profile_enable(int32_t on, int32_t max_launches) {

@@ -186,6 +186,12 @@ Workspace workspace_layout(const Geometry& g, int batch) {
     off = align256(off + B * plane);
     w.b_off = off;
     off = align256(off + B * plane);
+    // channels of LP levels 2..J, apart from level 1's, so that level 1's
+    // split passes can run beside the coarser levels
+    w.a2_off = off;
+    off = align256(off + (g.J > 1 ? B * plane / 4 : 0));
+    w.b2_off = off;
+    off = align256(off + (g.J > 1 ? B * plane / 4 : 0));
     w.part_off = off;
     off = align256(off + B * kMaxPart * 2 * sizeof(float));
     w.low_off = off;

@@ -45,6 +45,7 @@ struct Workspace {
     size_t d_off = 0;                      // [B][R][C]
     size_t a_off = 0;                      // [B][R][C]
     size_t b_off = 0;                      // [B][R][C]
+    size_t a2_off = 0, b2_off = 0;         // [B][R/2][C/2]: the channels of levels >= 2
     size_t part_off = 0;                   // quantiser partials [B][kMaxPart][2]
     size_t low_off = 0;                    // lowpass for the fused encoder [B][low_n]
     size_t total = 0;

@@ -77,6 +77,10 @@ int build_dequant_chain(const Geometry& g, int batch, const int16_t* idx, const 
                         std::vector<StageDesc>& chain);
 int launch_stage(const StageDesc& d, hipStream_t st);
 int launch_chain(const std::vector<StageDesc>& chain, hipStream_t st);
+// launch_chain with the level-1 split passes of a transform chain on a second
+// stream beside the coarser levels (same results); CT_SERIAL_LEVELS=1 in the
+// environment launches everything on `st` in chain order.
+int launch_chain_forked(const std::vector<StageDesc>& chain, hipStream_t st);
 int fill_quant_args(const Geometry& g, QuantArgs* a);
 int resident_waves();
 // Rows per streamed block of an LP-level stage and of a split stage.
