@@ -546,12 +546,17 @@ def main():
     step_traffic = None
     fused_bytes = None
     if not args.no_profile:
+        # per-launch times of each kernel on its own: the profiled steps run
+        # the chain in order on one stream (the timed steps above overlap the
+        # level-1 passes with the coarse levels, which stretches both)
+        os.environ["CT_SERIAL_LEVELS"] = "1"
         ct.profile_enable(True, 8192)
         for _ in range(args.steps):
             step()
         torch.cuda.synchronize()
         stats = ct.profile_collect(alg=True)
         ct.profile_enable(False)
+        del os.environ["CT_SERIAL_LEVELS"]
         total = sum(v[1] for v in stats.values())
         fused_bytes = sum(v[3] for v in stats.values()) / args.steps
         step_traffic = 0.0
