@@ -97,3 +97,47 @@ def test_fused_round_trip_against_oracle():
                             side[b].cpu().numpy().astype(np.float64), table)
         ref = oct.inverse(d, H, W, J, dirs)
         assert np.abs(rec[b] - ref).max() <= 1e-3
+
+
+@pytest.mark.parametrize("serial", ["0", "1"])
+def test_encode_decode_captured_in_a_graph(serial, monkeypatch):
+    """ct_encode + ct_decode captured into one HIP graph (the level-1 split
+    passes fork onto the library's second stream and join back inside the
+    capture), replayed three times with eager work in between: every replay
+    equals the eager results bit for bit, with and without the fork."""
+    from paper_1510_00561_amd import ct
+    monkeypatch.setenv("CT_SERIAL_LEVELS", serial)
+    H, W, J, dirs, B = 240, 320, 3, [32, 16, 8], 3
+    print(f"[fused] graph capture serial={serial}", flush=True)
+    rng = np.random.default_rng(77)
+    x = torch.from_numpy(rng.uniform(0, 255, (B, H, W)).astype(np.float32)).cuda()
+    plan = ct.Plan(H, W, J, dirs, B, "cuda")
+    steps = torch.from_numpy(rng.integers(4, 65, plan.nsub).astype(np.float32)).cuda()
+    idx = torch.empty((B, plan.ncoef), dtype=torch.int16, device="cuda")
+    side = torch.empty((B, 2), dtype=torch.float32, device="cuda")
+    out = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
+    plan.encode(x, steps, idx, side)
+    plan.decode(idx, steps, side, out=out)
+    torch.cuda.synchronize()
+    ref = (idx.clone(), side.clone(), out.clone())
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            plan.encode(x, steps, idx, side)
+            plan.decode(idx, steps, side, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.encode(x, steps, idx, side)
+        plan.decode(idx, steps, side, out=out)
+    for _ in range(3):
+        idx.zero_()
+        side.zero_()
+        out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(idx, ref[0]) and torch.equal(side, ref[1]) and torch.equal(out, ref[2])
+    del g
