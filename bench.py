@@ -118,7 +118,7 @@ def cpu_baseline(rgb_frames, steps_np, workers=None):
     t0 = time.perf_counter()
     _oracle_plane(jobs[0])
     latency = time.perf_counter() - t0
-    # a GPU machine gives this process a share of 16 cores, whatever the host count
+    # at most 16 worker processes (a share of a large host), one per core below that
     workers = workers or max(1, min(16, os.cpu_count() or 1))
     n = min(len(jobs), 3 * workers)
     ctx = mp.get_context("spawn")
