@@ -609,10 +609,16 @@ int launch_chain_forked(const std::vector<StageDesc>& chain, hipStream_t st) {
     std::lock_guard<std::mutex> lock(g_side_mu);
     Side& side = g_side[dev];
     if (!side.s) {
-        if (hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking) != hipSuccess) return CT_ERR_HIP;
-        if (hipEventCreateWithFlags(&side.fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&side.join, hipEventDisableTiming) != hipSuccess)
+        // all three or none
+        Side n;
+        if (hipStreamCreateWithFlags(&n.s, hipStreamNonBlocking) != hipSuccess) return CT_ERR_HIP;
+        if (hipEventCreateWithFlags(&n.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&n.join, hipEventDisableTiming) != hipSuccess) {
+            if (n.fork) hipEventDestroy(n.fork);
+            hipStreamDestroy(n.s);
             return CT_ERR_HIP;
+        }
+        side = n;
     }
     auto run = [&](size_t b, size_t e, hipStream_t s) -> int {
         for (size_t i = b; i < e; ++i) {
