@@ -612,6 +612,26 @@ def main():
                                     "roundtrip_max_abs_err": float((vrec - x).abs().max())}
             del vp, vrec
 
+    rgb_enc = None
+    if not args.no_extras:
+        # the encoder from the 8-bit frames: colour transform fused into the
+        # first LP level's loads, against the colour kernel + plane stacking
+        # + fused encoder
+        print("[bench] RGB encoder", file=sys.stderr, flush=True)
+
+        def enc_rgb():
+            plan.encode_rgb(rgb, steps, idx2, side2)
+
+        def enc_sep():
+            plan.encode(ycocg_planes(rgb), steps, idx, side)
+        ms_f, _ = timed(enc_rgb)
+        ms_s, _ = timed(enc_sep)
+        rgb_enc = {"workload": f"{FRAMES} RGB frames {W}x{H} -> indices of {PLANES} planes",
+                   "ms_fused": round(ms_f, 4), "ms_colour_then_encode": round(ms_s, 4),
+                   "frames_per_s_fused": round(FRAMES / (ms_f / 1e3), 1),
+                   "identical": bool(torch.equal(idx, idx2) and torch.equal(side, side2))}
+        plan.encode(x, steps, idx, side)      # the step's indices again, for the stages below
+
     fb = me = codec = None
     if not args.no_extras:
         print("[bench] colour and K-frame stages", file=sys.stderr, flush=True)
@@ -655,6 +675,7 @@ def main():
         "kernels": kernels,
         "batched": batched,
         "variants": variants,
+        "rgb_encoder": rgb_enc,
         "front_back": fb,
         "motion": me,
         "codec": codec,

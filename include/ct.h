@@ -228,6 +228,28 @@ int ct_decode(const ct_geom* geom, int32_t batch, const int16_t* idx, const floa
               void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Fused encoder from 8-bit RGB frames (section 3.1 front end, then section 3
+ * as ct_encode): the colour transform of equations (1)-(3) happens where the
+ * first LP level loads its rows, so neither the float planes nor the
+ * coefficients reach HBM. Results equal ct_rgb_to_ycocg with n = 1 followed
+ * by ct_encode on the 3 * frames planes ordered frame by frame as Y,
+ * Co + 127, Cg + 127, bit for bit.
+ *   frames     F >= 0 frames (3 * F <= 65535, 3 * F * H * W < 2^40), else
+ *              CT_ERR_ARG; F = 0 enqueues nothing.
+ *   rgb        uint8 [F][H][W][3], R, G, B interleaved (H, W from geom), no
+ *              alignment needed.
+ *   steps      as ct_encode, for batch 3 * F (steps_stride > 0: one row per
+ *              plane, plane 3 f + k is channel k of frame f).
+ *   idx, side  as ct_encode: [3 F][ncoef] int16 and [3 F][2] float.
+ *   ws         ct_workspace_bytes(geom, 3 * F) bytes.
+ * The chroma planes are full size: subsampled chroma (n > 1) goes through
+ * ct_rgb_to_ycocg and ct_encode on the smaller planes.
+ */
+int ct_encode_rgb(const ct_geom* geom, int32_t frames, const uint8_t* rgb, const float* steps,
+                  int32_t steps_stride, int16_t* idx, float* side, void* ws, size_t ws_bytes,
+                  hipStream_t stream);
+
+/*
  * Transposes for the differentiable form (gradients through the CT).
  * ct_forward_adjoint computes F^T g: gcoeffs [batch][ncoef] -> gplanes [batch][H][W].
  * ct_inverse_adjoint computes S^T g: gplanes [batch][H][W] -> gcoeffs [batch][ncoef].

@@ -232,7 +232,7 @@ static int first_subband(const Geometry& g, int j) {
 // and decoder); the float coefficients `out` / `in` may then be null.
 void build_transform_chain(const Geometry& g, int batch, int mode_i, const float* in, float* out,
                            char* ws, const Workspace& w, const int* tune,
-                           std::vector<StageDesc>& chain, const FusedQuant* fq) {
+                           std::vector<StageDesc>& chain, const FusedQuant* fq, const uint8_t* rgb) {
     const Mode mode = Mode(mode_i);
     const bool analysis = mode == Mode::Forward || mode == Mode::InverseAdjoint;
     const bool plain_filters = mode == Mode::Forward || mode == Mode::Inverse;
@@ -273,6 +273,7 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
                 a.src_h = g.H;
                 a.src_w = g.W;
                 a.pad_mode = mode == Mode::Forward ? kPadReflect : kPadZero;
+                a.rgb = mode == Mode::Forward ? rgb : nullptr;
             } else {
                 a.src = CView{reinterpret_cast<const float*>(ws + w.c_off[j - 1]), int64_t(Rj) * Cj, Cj};
                 a.src_h = Rj;
@@ -316,11 +317,14 @@ void build_transform_chain(const Geometry& g, int batch, int mode_i, const float
             // compulsory bytes: input, lowpass, the four channels (indices
             // and / or floats when they are the final subbands)
             const double chan = l == 2 ? (level ? 4.0 : 0.0) + (qio.idx ? 2.0 : 0.0) : 4.0;
-            d.bytes = batch * (4.0 * double(a.src_h) * a.src_w + 4.0 * double(Rj / 2) * (Cj / 2) +
+            // source bytes per pixel of a plane: a float, or (RGB encoder) the
+            // frame's 3 bytes, read once for each of its three planes
+            const double src_b = (j == 1 && a.rgb) ? 3.0 : 4.0;
+            d.bytes = batch * (src_b * double(a.src_h) * a.src_w + 4.0 * double(Rj / 2) * (Cj / 2) +
                                chan * double(Rj) * Cj);
             // algorithmic: the frame (level 1), the float lowpass when it is
             // the caller's output, the final subbands when this stage makes them
-            d.alg = batch * ((j == 1 ? 4.0 * double(a.src_h) * a.src_w : 0.0) +
+            d.alg = batch * ((j == 1 ? (a.rgb ? 1.0 : 4.0) * double(a.src_h) * a.src_w : 0.0) +
                              (j == g.J && coeffs ? 4.0 * double(Rj / 2) * (Cj / 2) : 0.0) +
                              (l == 2 ? chan * double(Rj) * Cj : 0.0));
             push(d);
@@ -933,6 +937,34 @@ int ct_encode(const ct_geom* geom, int32_t batch, const float* planes, const flo
     const float* low = coeffs ? coeffs : reinterpret_cast<const float*>(wsc + w.low_off);
     rc = build_lowpass_quant_chain(g, batch, low, coeffs ? g.ncoef : g.low_n, steps, steps_stride, idx,
                                    side, wsc, w, chain);
+    if (rc != CT_OK) return rc;
+    return launch_chain_forked(chain, stream);
+}
+
+int ct_encode_rgb(const ct_geom* geom, int32_t frames, const uint8_t* rgb, const float* steps,
+                  int32_t steps_stride, int16_t* idx, float* side, void* ws, size_t ws_bytes,
+                  hipStream_t stream) {
+    if (frames < 0 || frames > 65535 / 3) return CT_ERR_ARG;
+    const int32_t batch = 3 * frames;
+    Geometry g;
+    int rc = check_common(geom, batch, &g);
+    if (rc != CT_OK) return rc;
+    if (batch == 0) return CT_OK;
+    if (!rgb || !steps || !idx || !side || !ws) return CT_ERR_ARG;
+    if (steps_stride < 0 || (steps_stride > 0 && steps_stride < g.nsub)) return CT_ERR_ARG;
+    if (int64_t(frames) * g.H * g.W * 3 >= (int64_t(1) << 40)) return CT_ERR_ARG;
+    const Workspace w = workspace_layout(g, batch);
+    if (ws_bytes < w.total) return CT_ERR_WORKSPACE;
+    if (!constants(g.filters).ok) return CT_ERR_UNSUPPORTED;
+    if (fault_injected()) return CT_ERR_HIP;
+    char* wsc = static_cast<char*>(ws);
+    const FusedQuant fq{idx, steps, steps_stride, nullptr};
+    std::vector<StageDesc> chain;
+    int tune[kMaxLevels];
+    tuned_codes(g, batch, tune);
+    build_transform_chain(g, batch, kModeForward, nullptr, nullptr, wsc, w, tune, chain, &fq, rgb);
+    rc = build_lowpass_quant_chain(g, batch, reinterpret_cast<const float*>(wsc + w.low_off), g.low_n, steps,
+                                   steps_stride, idx, side, wsc, w, chain);
     if (rc != CT_OK) return rc;
     return launch_chain_forked(chain, stream);
 }

@@ -15,13 +15,14 @@ namespace {
 
 constexpr int NT_STREAM = 256;
 
-// One wavefront per (plane, column strip, row block).
-template <int LO_R, int UP_R, bool Q>
+// One wavefront per (plane, column strip, row block). RGB: level 1 of the
+// RGB encoder (the source is 8-bit RGB frames, converted on load).
+template <int LO_R, int UP_R, bool Q, bool RGB = false>
 __global__ __launch_bounds__(NT_STREAM) void stream_level_analysis_kernel(stage::LevelAnaArgs a) {
     using S = stream::StreamLevelAna<LO_R, UP_R, NT_STREAM>;
     __shared__ float smem[S::SMEM];
     S st(a);
-    st.template run_tile<Q>(xcd_remap(blockIdx.x, gridDim.x), smem);
+    st.template run_tile<Q, RGB>(xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
 template <int LO_R, int UP_R, bool Q>
@@ -64,6 +65,13 @@ hipError_t launch_level_analysis(const stage::LevelAnaArgs& a, int lo_r, hipStre
     constexpr int waves = NT_STREAM / 64;
     const int tiles = (level_items(a.R, a.C, a.batch, a.bh) + waves - 1) / waves;
     const bool q = a.q.idx != nullptr;
+    if (a.rgb) {
+        // the RGB encoder: forward filters, mirror padding
+        if (lo_r != 4 || a.pad_mode != kPadReflect) return hipErrorInvalidValue;
+        if (q) stream_level_analysis_kernel<4, 3, true, true><<<tiles, NT_STREAM, 0, st>>>(a);
+        else stream_level_analysis_kernel<4, 3, false, true><<<tiles, NT_STREAM, 0, st>>>(a);
+        return hipGetLastError();
+    }
     if (lo_r == 4 && !q) stream_level_analysis_kernel<4, 3, false><<<tiles, NT_STREAM, 0, st>>>(a);
     else if (lo_r == 4) stream_level_analysis_kernel<4, 3, true><<<tiles, NT_STREAM, 0, st>>>(a);
     else if (lo_r == 3 && !q) stream_level_analysis_kernel<3, 4, false><<<tiles, NT_STREAM, 0, st>>>(a);

@@ -61,9 +61,12 @@ void tuned_codes(const Geometry& g, int batch, int* codes /* [kMaxLevels] */);
 // cached choice), using the workspace as scratch, and records the choices in
 // the per-process table; codes[j - 1] receives level j's code.
 int tune_geometry(const Geometry& g, int batch, char* ws, const Workspace& w, hipStream_t st, int* codes);
+// With `rgb` (forward mode only) the level-1 stage reads the planes from
+// 8-bit RGB frames instead of `in`: plane b is channel b % 3 of frame b / 3.
 void build_transform_chain(const Geometry& g, int batch, int mode, const float* in, float* out,
                            char* ws, const Workspace& w, const int* tune,
-                           std::vector<StageDesc>& chain, const FusedQuant* fq = nullptr);
+                           std::vector<StageDesc>& chain, const FusedQuant* fq = nullptr,
+                           const uint8_t* rgb = nullptr);
 // Quantiser stages of the lowpass alone (fused encoder): `low` holds each
 // plane's lowpass at stride `low_plane`.
 int build_lowpass_quant_chain(const Geometry& g, int batch, const float* low, int64_t low_plane,

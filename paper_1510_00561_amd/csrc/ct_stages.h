@@ -22,6 +22,10 @@ struct LevelAnaArgs {
     int batch;
     int bh;                 // rows per streamed block, a multiple of 8
     QuantIO q;              // the four channels as indices (levels with 4 directions)
+    // level 1 of the RGB encoder: when set, plane b is channel b % 3 (Y,
+    // Co + 127, Cg + 127) of frame b / 3 of these 8-bit RGB frames
+    // (src_h x src_w pixels, R, G, B interleaved), converted on load
+    const uint8_t* rgb;
 };
 
 // DFB tree levels 1-2 + LP level, synthesis: the four channels `in` and the

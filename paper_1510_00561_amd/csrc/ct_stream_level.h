@@ -25,6 +25,7 @@
 // side of the 96 columns they store.
 #pragma once
 
+#include "ct_color_stages.h"
 #include "ct_quant_stages.h"
 #include "ct_stream.h"
 
@@ -98,20 +99,23 @@ struct StreamLevelAna {
     static constexpr int rslot(int rel) { return ((rel % RR) + RR) % RR; }
     static constexpr int cslot(int rel) { return ((rel % RC) + RC) % RC; }
 
-    // QOUT must match A.q.idx != nullptr (the launcher picks the kernel).
-    template <bool QOUT>
+    // QOUT must match A.q.idx != nullptr and RGB A.rgb != nullptr (the
+    // launcher picks the kernel).
+    template <bool QOUT, bool RGB = false>
     __device__ __forceinline__ void run_tile(int tile, float* smem) const {
         const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
         const int item = tile * WAVES + wave;
         if (item < items()) {
             float* T = smem + wave * WAVE_SMEM;
-            if (A.L.first_odd) run<1, QOUT>(item, T);
-            else run<0, QOUT>(item, T);
+            if (A.L.first_odd) run<1, QOUT, RGB>(item, T);
+            else run<0, QOUT, RGB>(item, T);
         }
     }
 
-    // QOUT: the four channels are final subbands quantised on store
-    template <int FO, bool QOUT>
+    // QOUT: the four channels are final subbands quantised on store. RGB:
+    // the source is the RGB frames, each plane one channel (forward
+    // transform, mirror padding).
+    template <int FO, bool QOUT, bool RGB>
     __device__ __forceinline__ void run(int item, float* T) const {
         const int ns = strips(), nb = blocks();
         const int b = item / (ns * nb);
@@ -130,9 +134,17 @@ struct StreamLevelAna {
         // source columns of the lane's two image columns (periodic, then
         // padded past the real frame); zero padding clears the loaded bits
         // with a mask, so every load is unconditional
-        const float* sp = A.src.p + b * A.src.plane;
+        const float* sp = RGB ? nullptr : A.src.p + b * A.src.plane;
         uint32_t sc[2];                             // byte offsets within a source row
         uint32_t mc[2];
+        // RGB source: frame b / 3, channel b % 3 as ((wr r + wg g) + wb b) + w0,
+        // the operations of equations (1)-(3) (exact in float32)
+        const uint8_t* fp = RGB ? A.rgb + int64_t(b / 3) * (3 * int64_t(A.src_h) * A.src_w) : nullptr;
+        const int ch = b - 3 * (b / 3);
+        const float wr = ch == 0 ? 0.25f : ch == 1 ? 0.5f : -0.25f;
+        const float wg = ch == 0 ? 0.5f : ch == 1 ? 0.f : 0.5f;
+        const float wb = ch == 0 ? 0.25f : ch == 1 ? -0.5f : -0.25f;
+        const float w0 = ch == 0 ? 0.f : color::kChromaOffset;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             int g = pmod(cb0 + 2 * lane + e, C);
@@ -142,7 +154,7 @@ struct StreamLevelAna {
                 mc[e] = 0u;
                 g = 0;
             }
-            sc[e] = 4u * uint32_t(g);
+            sc[e] = (RGB ? 3u : 4u) * uint32_t(g);
         }
         int xrow = pmod(S, R);                      // next row to load, modulo R
         auto load_row = [&](Pair& X) {
@@ -153,9 +165,23 @@ struct StreamLevelAna {
                 mr = 0u;
                 g = 0;
             }
-            const uint32_t* rp = reinterpret_cast<const uint32_t*>(sp + int64_t(g) * A.src.ld);
-            X.x = __uint_as_float(ld_at(rp, sc[0]) & (mr & mc[0]));
-            X.y = __uint_as_float(ld_at(rp, sc[1]) & (mr & mc[1]));
+            if constexpr (RGB) {
+                // reflect padding only: the masks are all ones
+                const uint8_t* rp = fp + int64_t(g) * (3 * A.src_w);
+                float v[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const float r = float(ld_at(rp, sc[e])), gg = float(ld_at(rp, sc[e] + 1u));
+                    const float bb = float(ld_at(rp, sc[e] + 2u));
+                    v[e] = __fadd_rn(__fadd_rn(__fadd_rn(__fmul_rn(wr, r), __fmul_rn(wg, gg)), __fmul_rn(wb, bb)), w0);
+                }
+                X.x = v[0];
+                X.y = v[1];
+            } else {
+                const uint32_t* rp = reinterpret_cast<const uint32_t*>(sp + int64_t(g) * A.src.ld);
+                X.x = __uint_as_float(ld_at(rp, sc[0]) & (mr & mc[0]));
+                X.y = __uint_as_float(ld_at(rp, sc[1]) & (mr & mc[1]));
+            }
             xrow = xrow + 1 == R ? 0 : xrow + 1;
         };
 

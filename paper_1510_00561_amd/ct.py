@@ -109,6 +109,7 @@ def _lib():
             "ct_dequantize": [G, i32, P, P, i32, P, P, P],
             "ct_encode": [G, i32, P, P, i32, P, P, P, P, sz, P],
             "ct_decode": [G, i32, P, P, i32, P, P, P, sz, P],
+            "ct_encode_rgb": [G, i32, P, P, i32, P, P, P, sz, P],
             "ct_rgb_to_ycocg": [i32, i32, i32, i32, P, P, P, P, P],
             "ct_ycocg_to_rgb": [i32, i32, i32, i32, P, P, P, P, P],
             "ct_lowpass_diff": [G, i32, P, i32, P],
@@ -406,6 +407,29 @@ class Plan:
                               ctypes.c_void_p(side.data_ptr()), ctypes.c_void_p(cptr),
                               ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, self._stream())
         _check("ct_encode", rc)
+        return idx, side
+
+    def encode_rgb(self, rgb, steps, idx=None, side=None):
+        """Fused colour transform + forward CT + quantise of uint8 RGB frames
+        rgb [F, H, W, 3] (the plan's batch is 3 F: planes Y, Co + 127,
+        Cg + 127 of each frame): (idx [3 F, ncoef] int16, side [3 F, 2])."""
+        B = self.batch
+        if B % 3:
+            raise ValueError("encode_rgb needs a plan whose batch is 3 * frames")
+        F = B // 3
+        self._check_tensor(rgb, (F, self.height, self.width, 3), torch.uint8, "rgb")
+        steps, stride = self._steps(steps)
+        if idx is None:
+            idx = torch.empty((B, self.ncoef), dtype=torch.int16, device=rgb.device)
+        if side is None:
+            side = torch.empty((B, 2), dtype=torch.float32, device=rgb.device)
+        self._check_tensor(idx, (B, self.ncoef), torch.int16, "idx")
+        self._check_tensor(side, (B, 2), torch.float32, "side")
+        rc = _lib().ct_encode_rgb(ctypes.byref(self.g), F, ctypes.c_void_p(rgb.data_ptr()),
+                                  ctypes.c_void_p(steps.data_ptr()), stride, ctypes.c_void_p(idx.data_ptr()),
+                                  ctypes.c_void_p(side.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                                  self.ws_bytes, self._stream())
+        _check("ct_encode_rgb", rc)
         return idx, side
 
     def decode(self, idx, steps, side, out=None):

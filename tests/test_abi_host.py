@@ -248,3 +248,22 @@ def test_autotune_validation(ct):
     bad = ct.geom(256, 256, 2, [32, 6])
     assert lib.ct_autotune(ctypes.byref(bad), 2, d, n.value, None) == -2
     assert lib.ct_autotune_clear() == 0
+
+
+def test_encode_rgb_validation(ct):
+    """ct_encode_rgb checks its arguments before any launch: the frame count
+    (negative, or 3 * frames past the batch limit), null pointers, the steps
+    stride, the workspace size for 3 * frames planes; zero frames is a no-op."""
+    lib = ct._lib()
+    g = ct.geom(256, 256, 2, [8, 4])
+    dummy = ctypes.c_void_p(0x1000)
+    need = ct.workspace_bytes(256, 256, 2, [8, 4], 6)
+    assert lib.ct_encode_rgb(ctypes.byref(g), -1, dummy, dummy, 0, dummy, dummy, dummy, need, None) == -1
+    assert lib.ct_encode_rgb(ctypes.byref(g), 21846, dummy, dummy, 0, dummy, dummy, dummy, 1 << 50, None) == -1
+    assert lib.ct_encode_rgb(ctypes.byref(g), 2, None, dummy, 0, dummy, dummy, dummy, need, None) == -1
+    assert lib.ct_encode_rgb(ctypes.byref(g), 2, dummy, dummy, 3, dummy, dummy, dummy, need, None) == -1
+    assert lib.ct_encode_rgb(ctypes.byref(g), 2, dummy, dummy, 0, dummy, dummy, dummy, need - 1, None) == -3
+    assert lib.ct_encode_rgb(ctypes.byref(g), 0, None, None, 0, None, None, None, 0, None) == 0
+    bad = ct.geom(256, 256, 2, [8, 4], filters="53")
+    bad.filters = 7
+    assert lib.ct_encode_rgb(ctypes.byref(bad), 1, dummy, dummy, 0, dummy, dummy, dummy, 1 << 40, None) == -2
