@@ -60,9 +60,29 @@ def algorithmic_bytes_per_plane(ncoef):
     return 8 * H * W + 20 * ncoef
 
 
+def _with_includes(files):
+    """The files and every local header they include, transitively, in a
+    fixed order."""
+    csrc = os.path.join(ROOT, "paper_1510_00561_amd", "csrc")
+    seen, todo = [], list(files)
+    while todo:
+        fn = todo.pop(0)
+        if fn in seen or not os.path.exists(os.path.join(csrc, fn)):
+            continue
+        seen.append(fn)
+        with open(os.path.join(csrc, fn)) as f:
+            for line in f:
+                line = line.strip()
+                if line.startswith('#include "') and "/" not in line:
+                    todo.append(line.split('"')[1])
+    return seen
+
+
 def source_digest(name):
+    """Digest of a kernel's sources (with the headers they include): a counter
+    summary taken from other sources is stale."""
     h = hashlib.sha256()
-    for fn in KERNEL_SOURCES.get(name, ()):
+    for fn in _with_includes(KERNEL_SOURCES.get(name, ())):
         with open(os.path.join(ROOT, "paper_1510_00561_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

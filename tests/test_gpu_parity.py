@@ -136,7 +136,9 @@ def test_quantiser_ties_and_limits():
     n = table[-1].offset + table[-1].size
     c = np.zeros((2, n), np.float32)
     c[0, :table[0].size] = 42.0                      # constant lowpass -> s = 0
-    vals = np.array([0.5, 1.5, 2.5, -0.5, -2.5, 0.49999997, 1e9, -1e9, 3.75], np.float32)
+    vals = np.array([0.5, 1.5, 2.5, -0.5, -2.5, 0.49999997, 1e9, -1e9, 3.75,
+                     np.inf, -np.inf, np.nan, -0.0, 1e-45, 32766.5, -32767.5, 8388607.5, -8388607.5,
+                     0.50000006, -1.4999999], np.float32)
     c[:, table[1].offset:table[1].offset + len(vals)] = vals
     c[1, :table[0].size] = np.linspace(-3, 7, table[0].size, dtype=np.float32)
     steps = np.ones(len(table), np.float32)
@@ -148,7 +150,9 @@ def test_quantiser_ties_and_limits():
         np.testing.assert_array_equal(idx_h[b], q_ref)
         assert tuple(side_h[b]) == tuple(np.float32(v) for v in s_ref)
     assert np.all(idx_h[0, :table[0].size] == 0)
-    assert list(idx_h[0, table[1].offset:table[1].offset + len(vals)]) == [1, 2, 3, -1, -3, 0, 32767, -32768, 4]
+    assert list(idx_h[0, table[1].offset:table[1].offset + len(vals)]) == [
+        1, 2, 3, -1, -3, 0, 32767, -32768, 4,
+        32767, -32768, 0, 0, 0, 32767, -32768, 32767, -32768, 1, -1]
 
 
 def _near_half_integers(table, steps, B, seed):
