@@ -401,7 +401,8 @@ def codec_back_end(plan, x, steps, reps):
     for name, (n, tms, by, al) in stats.items():
         us = tms / n * 1e3
         dev[name] = {"avg_launch_us": round(us, 2), "bytes_per_launch": by / n,
-                     "gbps": round(by / n / (us * 1e3), 1), "frac": round(by / n / (us * 1e3) / HBM_PEAK_GBPS, 4)}
+                     "gbps": round(by / n / (us * 1e3), 1), "frac": round(by / n / (us * 1e3) / HBM_PEAK_GBPS, 4),
+                     "traffic": measured_traffic(name, by / n, "traffic_codec_1080p.json")}
     k_sym_h, k_off_h = k_sym.cpu().numpy(), k_off.cpu().numpy()
     p_sym_h, p_off_h = p_sym.cpu().numpy(), p_off.cpu().numpy()
     sizes = {}
