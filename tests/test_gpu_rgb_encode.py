@@ -112,3 +112,42 @@ def test_encode_rgb_rejects_a_batch_not_of_frames():
     with pytest.raises(ValueError):
         plan.encode_rgb(torch.zeros((1, 64, 64, 3), dtype=torch.uint8, device="cuda"),
                         torch.ones(plan.nsub, device="cuda"))
+
+
+def test_encode_rgb_captured_in_a_graph():
+    """ct_encode_rgb + ct_decode captured into one HIP graph (with the fork of
+    the level-1 split passes), replayed three times with eager work in
+    between: every replay equals the eager results bit for bit."""
+    F, H, W, J, dirs = 2, 240, 320, 3, [32, 16, 8]
+    print("[rgb-encode] graph capture", flush=True)
+    plan = ct.Plan(H, W, J, dirs, 3 * F, "cuda")
+    rgb_d = torch.from_numpy(_rgb(F, H, W, 67)).cuda()
+    steps_d = torch.from_numpy(_steps(H, W, J, dirs, 68)).cuda()
+    idx = torch.empty((3 * F, plan.ncoef), dtype=torch.int16, device="cuda")
+    side = torch.empty((3 * F, 2), dtype=torch.float32, device="cuda")
+    out = torch.empty((3 * F, H, W), dtype=torch.float32, device="cuda")
+    plan.encode_rgb(rgb_d, steps_d, idx, side)
+    plan.decode(idx, steps_d, side, out=out)
+    torch.cuda.synchronize()
+    ref = (idx.clone(), side.clone(), out.clone())
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            plan.encode_rgb(rgb_d, steps_d, idx, side)
+            plan.decode(idx, steps_d, side, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.encode_rgb(rgb_d, steps_d, idx, side)
+        plan.decode(idx, steps_d, side, out=out)
+    for _ in range(3):
+        idx.zero_()
+        side.zero_()
+        out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(idx, ref[0]) and torch.equal(side, ref[1]) and torch.equal(out, ref[2])
+    del g
