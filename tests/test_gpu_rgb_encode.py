@@ -28,6 +28,7 @@ CASES = [
     ("odd", 1, 45, 61, 2, [8, 4], "97"),            # odd sizes, padded to 48 x 64
     ("split3", 1, 96, 128, 2, [32, 8], "97"),       # three tree levels in one pass at level 1
     ("legall", 2, 70, 90, 3, [16, 8, 4], "53"),     # the 5/3 variant (other level-1 kernel taps)
+    ("quant1", 2, 66, 100, 1, [4], "97"),           # four directions at level 1: indices stored by the RGB stage
 ]
 
 
