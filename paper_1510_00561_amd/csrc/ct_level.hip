@@ -25,12 +25,14 @@ __global__ __launch_bounds__(NT_STREAM) void stream_level_analysis_kernel(stage:
     st.template run_tile<Q, RGB>(xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
-template <int LO_R, int UP_R, bool Q>
+// LOWONLY: the coarsest level of the decoder, whose lowpass (only) arrives as
+// indices.
+template <int LO_R, int UP_R, bool Q, bool LOWONLY = false>
 __global__ __launch_bounds__(NT_STREAM) void stream_level_synthesis_kernel(stage::LevelSynArgs a) {
     using S = stream::StreamLevelSyn<LO_R, UP_R, NT_STREAM>;
     __shared__ float smem[S::SMEM];
     S st(a);
-    st.template run_tile<Q>(xcd_remap(blockIdx.x, gridDim.x), smem);
+    st.template run_tile<Q, LOWONLY>(xcd_remap(blockIdx.x, gridDim.x), smem);
 }
 
 // One wavefront per (plane, parent channel, column strip, row block); FO is
@@ -85,6 +87,7 @@ hipError_t launch_level_synthesis(const stage::LevelSynArgs& a, int lo_r, hipStr
     const int tiles = (level_items(a.R, a.C, a.batch, a.bh) + waves - 1) / waves;
     const bool q = a.q.idx != nullptr || a.lq.idx != nullptr;
     if (lo_r == 4 && !q) stream_level_synthesis_kernel<4, 3, false><<<tiles, NT_STREAM, 0, st>>>(a);
+    else if (lo_r == 4 && !a.q.idx) stream_level_synthesis_kernel<4, 3, true, true><<<tiles, NT_STREAM, 0, st>>>(a);
     else if (lo_r == 4) stream_level_synthesis_kernel<4, 3, true><<<tiles, NT_STREAM, 0, st>>>(a);
     else if (lo_r == 3 && !q) stream_level_synthesis_kernel<3, 4, false><<<tiles, NT_STREAM, 0, st>>>(a);
     else return hipErrorInvalidValue;

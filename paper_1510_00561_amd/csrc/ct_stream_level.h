@@ -401,20 +401,21 @@ struct StreamLevelSyn {
     static constexpr int hslot(int rel) { return ((rel % RH) + RH) % RH; }
     static constexpr int cslot(int rel) { return ((rel % RC) + RC) % RC; }
 
-    // QIN must match (A.q.idx or A.lq.idx) != nullptr (the launcher picks the kernel).
-    template <bool QIN>
+    // QIN must match (A.q.idx or A.lq.idx) != nullptr (the launcher picks the kernel);
+    // LOWONLY: only the lowpass is indices (A.q.idx null), fixed at compile time.
+    template <bool QIN, bool LOWONLY = false>
     __device__ __forceinline__ void run_tile(int tile, float* smem) const {
         const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
         const int item = tile * WAVES + wave;
         if (item < items()) {
             float* T = smem + wave * WAVE_SMEM;
-            if (A.L.first_odd) run<1, QIN>(item, T);
-            else run<0, QIN>(item, T);
+            if (A.L.first_odd) run<1, QIN, LOWONLY>(item, T);
+            else run<0, QIN, LOWONLY>(item, T);
         }
     }
 
     // QIN: the four channels and / or the lowpass are indices dequantised on load
-    template <int FO, bool QIN>
+    template <int FO, bool QIN, bool LOWONLY>
     __device__ __forceinline__ void run(int item, float* T) const {
         const int ns = strips(), nb = blocks();
         const int b = item / (ns * nb);
@@ -437,7 +438,7 @@ struct StreamLevelSyn {
 
         // the four channels as floats, or (decoder, levels with four
         // directions) as indices dequantised on load
-        const bool qin = QIN && A.q.idx != nullptr;
+        const bool qin = QIN && !LOWONLY && A.q.idx != nullptr;
         const float* h0 = qin ? nullptr : A.in.p[0] + b * A.in.plane;   // H a=-1: even rows, odd columns
         const float* h1 = qin ? nullptr : A.in.p[1] + b * A.in.plane;   // H a=0:  odd rows, even columns
         const float* v2 = qin ? nullptr : A.in.p[2] + b * A.in.plane;   // V a=0:  even rows, even columns
@@ -450,7 +451,7 @@ struct StreamLevelSyn {
         const float d0 = qin ? qst[0] : 1.f, d1 = qin ? qst[1] : 1.f;
         const float d2 = qin ? qst[2] : 1.f, d3 = qin ? qst[3] : 1.f;
         // the lowpass c_in as floats, or (decoder, coarsest level) as indices
-        const bool lin = QIN && A.lq.idx != nullptr;
+        const bool lin = QIN && (LOWONLY || A.lq.idx != nullptr);
         const float* cin = lin ? nullptr : A.c_in.p + b * A.c_in.plane;
         const int16_t* lx = lin ? A.lq.idx + b * A.lq.plane : nullptr;
         float l_mn = 0.f, l_step = 1.f, l_r = 0.f;
