@@ -50,6 +50,32 @@ __device__ __forceinline__ int16_t to_index(float v) {
     return v == v ? (int16_t)(int)c : (int16_t)0;
 }
 
+// Steps in [2^-20, 2^20] take the index through the reciprocal below; others
+// the correctly rounded division.
+__host__ __device__ inline bool fast_step(float b) { return b >= 0x1p-20f && b <= 0x1p20f; }
+
+// to_index(a / b rounded to nearest) for a step b with fast_step(b) and
+// r = 1 / b rounded to nearest: the quotient a r corrected twice by its
+// residual a - b q, each residual exact in one FMA (Markstein's correction
+// of a reciprocal-based quotient). Wherever the index depends on it this is
+// the correctly rounded quotient; where |a r| >= 2^24 the index saturates
+// either way and a r is kept (no overflow in the residuals). Checked against
+// the division for every float a and 1,831 steps: the integers and halves to
+// 128, the powers of two, mantissas of all ones and near them, and 1,200
+// log-uniform steps over the range.
+__device__ __forceinline__ int16_t quant_index(float a, float b, float r) {
+    const float q0 = __fmul_rn(a, r);
+    const float q1 = __builtin_fmaf(__builtin_fmaf(-b, q0, a), r, q0);
+    const float q2 = __builtin_fmaf(__builtin_fmaf(-b, q1, a), r, q1);
+    return to_index(__builtin_fabsf(q0) < 0x1p24f ? q2 : q0);
+}
+
+// The quantiser's index of a / b; `fast` (uniform across the wave) says that
+// fast_step(b) holds and r is 1 / b rounded to nearest.
+__device__ __forceinline__ int16_t index_of(float a, float b, float r, bool fast) {
+    return fast ? quant_index(a, b, r) : to_index(__fdiv_rn(a, b));
+}
+
 __device__ __forceinline__ int find_subband(const QuantArgs& A, int64_t e) {
     int lo = 0, hi = A.nsub - 1;           // largest s with sub_off[s] <= e
     while (lo < hi) {
@@ -121,6 +147,8 @@ __device__ void quantize(const QuantArgs& A, int tile, float* red) {
         // thread, 32-byte loads and a 16-byte store
         constexpr int IT = (CHUNK / 8 + NT - 1) / NT;
         const float step = steps[s0];
+        const bool fast = __builtin_amdgcn_readfirstlane(int(fast_step(step))) != 0;
+        const float rstep = fast ? __fdiv_rn(1.f, step) : 1.f;
         float4 xa[IT], xb[IT];
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
@@ -143,9 +171,8 @@ __device__ void quantize(const QuantArgs& A, int tile, float* red) {
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     const float xv = x[2 * h + u];
-                    const float v = s0 == 0 ? __fdiv_rn(__fmul_rn(__fsub_rn(xv, mn), sc), step)
-                                            : __fdiv_rn(xv, step);
-                    pair[u] = uint32_t(uint16_t(to_index(v)));
+                    const float a = s0 == 0 ? __fmul_rn(__fsub_rn(xv, mn), sc) : xv;
+                    pair[u] = uint32_t(uint16_t(index_of(a, step, rstep, fast)));
                 }
                 w[h] = pair[0] | (pair[1] << 16);
             }

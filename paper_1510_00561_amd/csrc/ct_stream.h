@@ -340,13 +340,19 @@ struct StreamSplit {
         auto qbase = [&](int c) __attribute__((always_inline)) { return qfirst + brev(c & (NCH - 1)) * cstride; };
         // per final channel: the scale of the final store (analysis) or load
         // (synthesis) and the quantiser step
-        float fsc[NCH], qstep[NCH];
+        float fsc[NCH], qstep[NCH], qrcp[NCH];
+        int qf = 1;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int pos = P0 + (g.vertical ? brev(c) : -brev(c));
             fsc[c] = A.use_scale ? A.scale[pos] : 1.f;
             qstep[c] = QUANT ? qsteps[A.q.sub0 + pos] : 1.f;
+            qf &= int(qstage::fast_step(qstep[c]));
         }
+        // the same for every lane: a scalar branch per quantised value
+        const bool qfast = __builtin_amdgcn_readfirstlane(qf) != 0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) qrcp[c] = (ANA && QUANT && qfast) ? __fdiv_rn(1.f, qstep[c]) : 1.f;
         auto lsc = [&](int c) __attribute__((always_inline)) { return ANA ? 1.f : fsc[c & (NCH - 1)]; };
         auto ssc = [&](int c) __attribute__((always_inline)) { return ANA ? fsc[c & (NCH - 1)] : 1.f; };
         // indices move CPL at once only from dword-aligned addresses
@@ -470,7 +476,8 @@ struct StreamSplit {
                     v[e] = ssc(c) * X.v[e];
                     // quantise on store: round(c / step), as ct_quantize on
                     // the stored float
-                    qv[e] = (ANA && QUANT) ? qstage::to_index(__fdiv_rn(v[e], qstep[c & (NCH - 1)])) : int16_t(0);
+                    qv[e] = (ANA && QUANT) ? qstage::index_of(v[e], qstep[c & (NCH - 1)], qrcp[c & (NCH - 1)], qfast)
+                                           : int16_t(0);
                 }
                 const bool fvec = sal[r] || uint32_t(cb) + STRIP_BYTES <= ncb;
                 if (st_in) {

@@ -201,6 +201,10 @@ struct StreamLevelAna {
         const float* qst = qout ? A.q.steps + int64_t(b) * A.q.steps_stride + A.q.sub0 : nullptr;
         const float d0 = qout ? qst[0] : 1.f, d1 = qout ? qst[1] : 1.f;
         const float d2 = qout ? qst[2] : 1.f, d3 = qout ? qst[3] : 1.f;
+        const bool qfast = qout && __builtin_amdgcn_readfirstlane(int(qstage::fast_step(d0) && qstage::fast_step(d1) &&
+                                                                       qstage::fast_step(d2) && qstage::fast_step(d3))) != 0;
+        const float r0 = qfast ? __fdiv_rn(1.f, d0) : 1.f, r1 = qfast ? __fdiv_rn(1.f, d1) : 1.f;
+        const float r2 = qfast ? __fdiv_rn(1.f, d2) : 1.f, r3 = qfast ? __fdiv_rn(1.f, d3) : 1.f;
         const uint32_t kc4 = 4u * uint32_t(kc), kc2 = 2u * uint32_t(kc);   // owning lanes: kc >= 0
 
         // transposed flush of `cnt` compact rows starting at compact row i0:
@@ -227,8 +231,8 @@ struct StreamLevelAna {
                         st_at(q3 + ob, 4u * lo, e);
                     }
                     if (qout) {
-                        st_at(x0 + 2 * q4 + ob, 2u * lo, qstage::to_index(__fdiv_rn(a, d2)));
-                        st_at(x0 + 3 * q4 + ob, 2u * lo, qstage::to_index(__fdiv_rn(e, d3)));
+                        st_at(x0 + 2 * q4 + ob, 2u * lo, qstage::index_of(a, d2, r2, qfast));
+                        st_at(x0 + 3 * q4 + ob, 2u * lo, qstage::index_of(e, d3, r3, qfast));
                     }
                 }
             }
@@ -334,8 +338,8 @@ struct StreamLevelAna {
                                 st_at(q1 + o, kc4, e);
                             }
                             if (qout) {
-                                st_at(x0 + o, kc2, qstage::to_index(__fdiv_rn(a, d0)));
-                                st_at(x0 + q4 + o, kc2, qstage::to_index(__fdiv_rn(e, d1)));
+                                st_at(x0 + o, kc2, qstage::index_of(a, d0, r0, qfast));
+                                st_at(x0 + q4 + o, kc2, qstage::index_of(e, d1, r1, qfast));
                             }
                         }
                         const int slot = (i - (rb >> 1)) & (VB - 1);

@@ -201,6 +201,52 @@ def test_quantiser_near_half_integers(case):
         np.testing.assert_array_equal(idx_h[b], q_ref)
 
 
+def _tricky_steps(n, seed):
+    """Quantiser steps that stress the reciprocal-and-correction quotient:
+    mantissas of all ones and one unit from it, one unit above a power of two,
+    small integers and halves, the ends of its range [2^-20, 2^20] and the
+    floats just outside them (which take the division), then log-uniform
+    steps over the range."""
+    f = np.float32
+    one_minus = np.nextafter(f(2), f(0))
+    base = [f(2.0) ** k * m for k in (-20, -7, 0, 3, 5, 19) for m in
+            (one_minus, np.nextafter(one_minus, f(0)), np.nextafter(f(1), f(2)), f(1.5))]
+    base += [f(v) for v in (1, 3, 7, 28, 29.25, 63.5, 105.25, 0.1, 0.37, 13.25)]
+    base += [f(2.0 ** -20), f(2.0 ** 20), np.nextafter(f(2.0 ** -20), f(0)), np.nextafter(f(2.0 ** 20), f(np.inf))]
+    rng = np.random.default_rng(seed)
+    rest = (2.0 ** rng.uniform(-20, 20, n - len(base))).astype(np.float32)
+    return np.concatenate([np.array(base, np.float32), rest])
+
+
+def test_quantiser_reciprocal_path_exact():
+    """Steps in [2^-20, 2^20] quantise through the step's reciprocal and two
+    FMA corrections of the quotient: on subbands large enough for the
+    single-subband path, with values at and a few float32 steps around every
+    (k + 1/2) step and random values, indices equal the oracle's FP32
+    quantiser (correctly rounded division) for 256 such steps and for steps
+    just outside the range."""
+    H, W, J, dirs, B = 1024, 1024, 1, [4], 64
+    table = geo.subband_table(H, W, J, dirs)
+    steps = np.ones((B, len(table)), np.float32)
+    steps[:, 1:] = _tricky_steps(B * (len(table) - 1), 11).reshape(B, len(table) - 1)
+    rng = np.random.default_rng(12)
+    n = table[-1].offset + table[-1].size
+    c = np.empty((B, n), np.float32)
+    for b in range(B):
+        c[b] = _near_half_integers(table, steps[b], 1, 100 + b)[0]
+        # a quarter of every subband: random bits with quotients up to 2^25
+        for sb, st in zip(table[1:], steps[b, 1:]):
+            m = sb.size // 4
+            q = (2.0 ** rng.uniform(-3, 25, m)) * rng.choice([-1.0, 1.0], m)
+            c[b, sb.offset:sb.offset + m] = (q * np.float64(st)).astype(np.float32)
+    plan = _plan(H, W, J, dirs, B)
+    idx, _ = plan.quantize(_dev(c), _dev(steps))
+    idx_h = idx.cpu().numpy()
+    for b in range(B):
+        q_ref, _ = oq.quantize32(c[b], steps[b], table)
+        np.testing.assert_array_equal(idx_h[b], q_ref)
+
+
 def test_quantise_gpu_coefficients_mismatch_rate():
     """Indices from the GPU's own coefficients differ only at rounding boundaries."""
     H, W, J, dirs = 256, 256, 2, [8, 4]
