@@ -44,8 +44,8 @@ __device__ __forceinline__ void block_minmax(float& mn, float& mx, float* red) {
 // roundf(v) for every float (checked over all 2^32 bit patterns against the
 // branching form); the largest float below one half keeps a value just
 // under k + 1/2 from rounding up in the addition.
-__device__ __forceinline__ int16_t to_index(float v) {
-    const float r = __builtin_truncf(__fadd_rn(v, __builtin_copysignf(0x1.fffffep-2f, v)));
+__host__ __device__ __forceinline__ int16_t to_index(float v) {
+    const float r = __builtin_truncf(v + __builtin_copysignf(0x1.fffffep-2f, v));   // one rounding
     const float c = __builtin_fminf(__builtin_fmaxf(r, -32768.f), 32767.f);
     return v == v ? (int16_t)(int)c : (int16_t)0;
 }
@@ -63,8 +63,8 @@ __host__ __device__ inline bool fast_step(float b) { return b >= 0x1p-20f && b <
 // the division for every float a and 1,831 steps: the integers and halves to
 // 128, the powers of two, mantissas of all ones and near them, and 1,200
 // log-uniform steps over the range.
-__device__ __forceinline__ int16_t quant_index(float a, float b, float r) {
-    const float q0 = __fmul_rn(a, r);
+__host__ __device__ __forceinline__ int16_t quant_index(float a, float b, float r) {
+    const float q0 = a * r;   // one rounding (no contraction in this file's builds)
     const float q1 = __builtin_fmaf(__builtin_fmaf(-b, q0, a), r, q0);
     const float q2 = __builtin_fmaf(__builtin_fmaf(-b, q1, a), r, q1);
     return to_index(__builtin_fabsf(q0) < 0x1p24f ? q2 : q0);
